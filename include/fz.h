@@ -1,0 +1,129 @@
+/*
+ * fz.h -- C ABI of libfzmi, an MI355X (gfx950) implementation of the FZ-GPU
+ * compression hot path:
+ *   dual-quantization (prequantize to the 2*eb grid, then Lorenzo prediction
+ *   on the integers), 16-bit sign-magnitude codes, bitshuffle, and the
+ *   zero-block encoder (flags, device-wide prefix sum, compaction), plus the
+ *   matching decompressor.
+ *
+ * Paper: Zhang et al., "FZ-GPU: A Fast and High-Ratio Lossy Compressor for
+ * Scientific Computing Applications on GPUs", HPDC'23.  The problem statement
+ * (Sec. 2.4) fixes the setting: the field is produced in GPU memory and
+ * compressed there; the compressed bytes either stay in GPU memory for a
+ * later GPU decompression or are copied out.  Input is fp32 (Sec. 4.1,
+ * Table 1); the error bound is absolute or relative to the value range
+ * (Sec. 4.1).
+ *
+ * Conventions for every call:
+ *   - pointers named d_* are device pointers (HIP device memory of the
+ *     current device); h_* are host pointers;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls only enqueue work on it and never synchronize the host;
+ *   - the caller owns every buffer; the library allocates nothing per call
+ *     and keeps no state between calls; calls on different streams are
+ *     independent as long as their buffers do not overlap;
+ *   - argument errors return a nonzero fz_status immediately and enqueue
+ *     nothing; data-dependent errors are reported on the device (see each
+ *     call).
+ */
+#ifndef FZ_H
+#define FZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FZ_OK = 0,
+    FZ_ERR_ARG = 1,          /* invalid argument (returned immediately) */
+    FZ_ERR_HIP = 2,          /* a HIP runtime call failed */
+    FZ_ERR_NONFINITE = 3,    /* input holds NaN or Inf */
+    FZ_ERR_EB_RANGE = 4,     /* error bound unusable: 2*eb not a normal fp32, or |x/(2eb)| >= 2^31 */
+    FZ_ERR_OUTLIER_CAP = 5,  /* more than 256 escaped codes in one layer of 8192 codes */
+    FZ_ERR_STREAM = 6,       /* malformed or inconsistent stream */
+    FZ_ERR_VERSION = 7,      /* unknown stream version */
+    FZ_ERR_STATUS = 8        /* stream carries a nonzero compression status */
+} fz_status;
+
+typedef enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 } fz_eb_mode;
+
+/* Field extents, slowest-varying first (a 3-D field 100 x 500 x 500 has
+ * n = {100, 500, 500}; x is the contiguous dimension).  rank is 1, 2 or 3;
+ * n[rank..2] are ignored. */
+typedef struct {
+    uint32_t rank;
+    uint32_t reserved;
+    uint64_t n[3];
+} fz_dims;
+
+/* Parsed stream header (host side). */
+typedef struct {
+    uint32_t version;
+    uint32_t status;      /* OR of FZ_STATUS_BIT_* set during compression */
+    uint32_t rank;
+    uint32_t eb_mode;
+    uint64_t n[3];
+    double eb_user;
+    float ebx2;           /* fp32(2 * absolute error bound) */
+    float inv;            /* fp32(1 / ebx2) */
+    float vmin, vmax;     /* value range (REL mode; 0 in ABS mode) */
+    uint32_t n_chunks;
+    uint64_t nnz_blocks;  /* nonzero 16-byte blocks stored */
+    uint64_t n_outliers;  /* escaped codes stored as (index, value) pairs */
+    uint64_t total_bytes; /* stream size */
+    uint64_t header_bytes;/* header + chunk table + flags */
+} fz_info;
+
+/* status bits written into the header by the device */
+#define FZ_STATUS_BIT_NONFINITE 1u
+#define FZ_STATUS_BIT_EB_RANGE 2u
+#define FZ_STATUS_BIT_OUTLIER_CAP 4u
+
+/* Bytes the caller must provide as d_out of fz_compress: the worst-case
+ * stream (every data block nonzero plus the escape cap) followed by the
+ * scratch the single-pass prefix sum uses.  0 on invalid dims. */
+size_t fz_compress_bound(const fz_dims *dims);
+
+/* Bytes of header + chunk table + flags; depends only on the dims. */
+size_t fz_header_bytes(const fz_dims *dims);
+
+/* fz_compress -- Sec. 3.1's pipeline in one pass over the input.
+ *   d_in   : N fp32 values, row-major, slowest-first dims (device, read only)
+ *   dims   : host pointer
+ *   eb     : absolute error bound (FZ_EB_ABS) or bound relative to the value
+ *            range max-min (FZ_EB_REL, Sec. 4.1); must be finite and > 0
+ *   d_out  : device buffer of at least fz_compress_bound(dims) bytes; on
+ *            completion it starts with the stream, whose size is the header's
+ *            total_bytes field (little-endian u64 at byte 96)
+ * Every reconstructed value differs from the input by at most the error bound
+ * (Sec. 2.3 inequality) up to fp32 rounding of x/(2eb) and of q*2eb.
+ * Data-dependent errors (NaN/Inf, |x/(2eb)| >= 2^31, escape cap) set bits of
+ * the header's status word (u32 at byte 8); the rest of the stream is then
+ * unspecified.  Returns FZ_OK once the work is enqueued. */
+int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
+
+/* fz_decompress -- the inverse pipeline (Sec. 4.3 describes it as symmetric
+ * to compression).
+ *   d_stream : device pointer to a stream made by fz_compress
+ *   d_out    : N fp32 values (device, written)
+ *   dims     : must equal the dims the stream was made with
+ *   d_err    : optional device u32; receives 0 or an fz_status code
+ *              (FZ_ERR_STREAM, FZ_ERR_VERSION, FZ_ERR_STATUS) if the stream
+ *              is rejected on the device; d_out is then not written
+ * Returns FZ_OK once the work is enqueued. */
+int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
+
+/* Parse a host copy of the first n >= 128 bytes of a stream. */
+int fz_stream_info(const void *h_header, size_t n, fz_info *out);
+
+/* Human-readable name of an fz_status. */
+const char *fz_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FZ_H */

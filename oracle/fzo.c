@@ -60,7 +60,8 @@
 #define FZO_CHUNK_CODES (FZO_STEPS * FZO_STEP_CODES)
 #define FZO_PLANES 16
 #define FZO_FLAG_BYTES_PER_CHUNK (FZO_LAYERS * FZO_PLANES * 8)
-#define FZO_OUTLIER_CAP 1024
+#define FZO_OUTLIER_CAP 1024       /* per chunk (= 4 layers x 256) */
+#define FZO_LAYER_OUTLIER_CAP 256  /* per layer: 1/32 of its 8192 codes */
 #define FZO_ESCAPE 0x8000u
 
 typedef struct {
@@ -164,12 +165,13 @@ int fzo_eb_params(const float *x, int64_t n, double eb, int eb_mode,
 {
     float lo = 0.0f, hi = 0.0f;
     int status = 0;
-    if (n > 0 && eb_mode == FZO_EB_REL) { lo = x[0]; hi = x[0]; }
+    if (n > 0 && eb_mode == FZO_EB_REL) { lo = x[0] == 0.0f ? 0.0f : x[0]; hi = lo; }
     /* the value range is only needed (and only recorded) in REL mode */
     for (int64_t i = 0; i < (eb_mode == FZO_EB_REL ? n : 0); i++) {
         if (!isfinite(x[i])) { status |= FZO_ERR_NONFINITE; continue; }
-        if (!isfinite(lo) || x[i] < lo) lo = x[i];
-        if (!isfinite(hi) || x[i] > hi) hi = x[i];
+        float v = x[i] == 0.0f ? 0.0f : x[i]; /* -0 counts as +0 */
+        if (!isfinite(lo) || v < lo) lo = v;
+        if (!isfinite(hi) || v > hi) hi = v;
     }
     *vmin = lo; *vmax = hi;
     double eb_abs = eb;
@@ -362,8 +364,14 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
 #pragma omp parallel for schedule(dynamic, 1) if (threads != 1)
 #endif
         for (int64_t c = 0; c < g.n_chunks; c++) encode_chunk(&g, q, c, &co[c]);
-        for (int64_t c = 0; c < g.n_chunks; c++)
+        /* at most 256 escapes per layer (8192 codes) */
+        for (int64_t c = 0; c < g.n_chunks; c++) {
+            int64_t per_layer[FZO_LAYERS] = {0, 0, 0, 0};
             if (co[c].nout > FZO_OUTLIER_CAP) status |= FZO_ERR_OUTLIER_CAP;
+            for (int64_t i = 0; i < co[c].nout && i < FZO_OUTLIER_CAP; i++) per_layer[co[c].oidx[i] / (4 * FZO_STEP_CODES)]++;
+            for (int k = 0; k < FZO_LAYERS; k++)
+                if (per_layer[k] > FZO_LAYER_OUTLIER_CAP) status |= FZO_ERR_OUTLIER_CAP;
+        }
     }
     (void)threads;
 

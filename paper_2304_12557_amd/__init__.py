@@ -1,0 +1,163 @@
+"""Python binding of libfzmi (the MI355X FZ-GPU hot path).
+
+Argument marshalling only: every step of compression and decompression runs
+in the HIP kernels of ``libfzmi.so``.  torch supplies device memory and the
+current HIP stream.  If the shared library is missing the import of any
+function here raises; there is no CPU fallback.
+
+    s = compress(x, 1e-3)                 # x: float32 CUDA tensor, REL eb
+    n = stream_size(s)                    # reads the 128-byte header (syncs)
+    y = decompress(s, x.shape)            # float32 CUDA tensor
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfzmi.so")
+
+FZ_EB_ABS = 0
+FZ_EB_REL = 1
+STATUS_NONFINITE = 1
+STATUS_EB_RANGE = 2
+STATUS_OUTLIER_CAP = 4
+ERRORS = {0: "ok", 1: "invalid argument", 2: "HIP runtime error", 3: "input holds NaN or Inf",
+          4: "error bound out of range", 5: "too many escaped codes", 6: "malformed stream",
+          7: "unsupported stream version", 8: "stream carries a compression error"}
+
+_LIB = None
+
+
+class FzDims(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("n", ctypes.c_uint64 * 3)]
+
+
+class FzInfo(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_uint32), ("status", ctypes.c_uint32), ("rank", ctypes.c_uint32),
+                ("eb_mode", ctypes.c_uint32), ("n", ctypes.c_uint64 * 3), ("eb_user", ctypes.c_double),
+                ("ebx2", ctypes.c_float), ("inv", ctypes.c_float), ("vmin", ctypes.c_float),
+                ("vmax", ctypes.c_float), ("n_chunks", ctypes.c_uint32), ("nnz_blocks", ctypes.c_uint64),
+                ("n_outliers", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
+                ("header_bytes", ctypes.c_uint64)]
+
+
+class FzError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__("%s: %s (%d)" % (what, ERRORS.get(code, "unknown"), code))
+        self.code = code
+
+
+def lib():
+    """Load libfzmi.so from the package directory (build it with build.py)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfzmi.so is not built; run `python -m paper_2304_12557_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        dp = ctypes.POINTER(FzDims)
+        L.fz_compress_bound.argtypes = [dp]
+        L.fz_compress_bound.restype = ctypes.c_size_t
+        L.fz_header_bytes.argtypes = [dp]
+        L.fz_header_bytes.restype = ctypes.c_size_t
+        L.fz_compress.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
+        L.fz_compress.restype = ctypes.c_int
+        L.fz_decompress.argtypes = [vp, vp, dp, vp, vp]
+        L.fz_decompress.restype = ctypes.c_int
+        L.fz_stream_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(FzInfo)]
+        L.fz_stream_info.restype = ctypes.c_int
+        L.fz_strerror.argtypes = [ctypes.c_int]
+        L.fz_strerror.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror"]
+
+
+def dims_of(shape):
+    shape = tuple(int(s) for s in shape)
+    if not 1 <= len(shape) <= 3:
+        raise ValueError("rank must be 1, 2 or 3")
+    d = FzDims()
+    d.rank = len(shape)
+    for i in range(3):
+        d.n[i] = shape[i] if i < len(shape) else 1
+    return d
+
+
+def compress_bound(shape):
+    return int(lib().fz_compress_bound(ctypes.byref(dims_of(shape))))
+
+
+def header_bytes(shape):
+    return int(lib().fz_header_bytes(ctypes.byref(dims_of(shape))))
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mode(mode):
+    if mode in ("rel", FZ_EB_REL):
+        return FZ_EB_REL
+    if mode in ("abs", FZ_EB_ABS):
+        return FZ_EB_ABS
+    raise ValueError("mode must be 'rel' or 'abs'")
+
+
+def compress(x, eb, mode="rel", out=None, stream=None):
+    """Compress a float32 CUDA tensor; returns the uint8 output buffer
+    (``compress_bound`` bytes; the stream occupies its first
+    ``stream_size(buf)`` bytes).  Asynchronous on ``stream``."""
+    import torch
+
+    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    dims = dims_of(x.shape)
+    bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
+    if out is None:
+        out = torch.empty(bound, dtype=torch.uint8, device=x.device)
+    elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
+        raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
+    rc = lib().fz_compress(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
+                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    if rc:
+        raise FzError(rc, "fz_compress")
+    return out
+
+
+def decompress(s, shape, out=None, err=None, stream=None):
+    """Decompress a stream held in a uint8 CUDA tensor into float32.  If
+    ``err`` (a 1-element int32 CUDA tensor) is given it receives 0 or the
+    error code of a stream rejected on the device."""
+    import torch
+
+    dims = dims_of(shape)
+    if out is None:
+        out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
+    rc = lib().fz_decompress(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims),
+                             ctypes.c_void_p(err.data_ptr() if err is not None else 0), _stream_ptr(stream))
+    if rc:
+        raise FzError(rc, "fz_decompress")
+    return out
+
+
+def stream_info(header):
+    """Parse the header from host bytes (or a CUDA tensor, which is copied)."""
+    if hasattr(header, "is_cuda"):
+        header = header[:128].cpu().numpy().tobytes()
+    buf = (ctypes.c_uint8 * len(header)).from_buffer_copy(bytes(header))
+    info = FzInfo()
+    rc = lib().fz_stream_info(ctypes.cast(buf, ctypes.c_void_p), len(header), ctypes.byref(info))
+    if rc:
+        raise FzError(rc, "fz_stream_info")
+    return {f: (list(getattr(info, f)) if f == "n" else getattr(info, f)) for f, _ in FzInfo._fields_}
+
+
+def stream_size(buf):
+    """Total stream bytes, read from the header of a compressed buffer."""
+    return int(stream_info(buf)["total_bytes"])

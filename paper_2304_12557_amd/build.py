@@ -1,0 +1,49 @@
+"""Builds libfzmi.so (HIP, gfx950) in-tree with hipcc.
+
+Flags: -O3, fp contraction off, fp32 denormals kept, packed-fp32 instructions
+disabled.  Usage: python -m paper_2304_12557_amd.build  (or build()).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = ["fz_api.hip", "fz_compress.hip", "fz_decompress.hip"]
+LIB = os.path.join(HERE, "libfzmi.so")
+ARCH = os.environ.get("FZ_OFFLOAD_ARCH", "gfx950")
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off", "-fno-fast-math",
+    "-fno-gpu-flush-denormals-to-zero", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def build(verbose=False, extra=()):
+    objs = []
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    procs = []
+    for s in SRC:
+        o = os.path.join(bdir, s.replace(".hip", ".o"))
+        cmd = ["hipcc", "-c", os.path.join(HERE, "csrc", s), "-o", o] + FLAGS + list(extra)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), s))
+        objs.append(o)
+    for p, s in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out.decode())
+            raise RuntimeError("hipcc failed on " + s)
+        if verbose and out:
+            sys.stderr.write(out.decode())
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,106 @@
+// fz_format.hpp -- stream format v1 constants and chunk geometry (device +
+// host side of libfzmi).
+//
+// Stream layout (little-endian):
+//   header (128 B) | chunk table (8 B per chunk, padded to 16 B) |
+//   flags (512 B per chunk) | payload (16-B units)
+// A chunk is the unit of independent decompression: the Lorenzo predictor
+// (Sec. 2.3) runs inside its box with zero ghosts at the box faces.  Boxes
+// (slowest-first): 3-D 16 x 32 x 64, 2-D 32 x 1024, 1-D 32768 values.
+// A chunk holds up to 16 steps of 2048 codes (64 patches of 32 codes), and
+// 4 steps form a layer.  The data block of the zero-block encoder (Sec. 3.4)
+// is a brick: one bit plane of one patch over the 4 steps of a layer
+// (128 bits), i.e. the bitshuffle of Sec. 3.3 gathers bit b of 128 codes that
+// are neighbours in space (3-D: a 4x4x8 box; 2-D: 8x16; 1-D: 4 runs of 32).
+//   code index n = step*2048 + patch*32 + cell
+//   3-D: z = step, y = 4*(patch%8) + cell/8, x = 8*(patch/8) + cell%8
+//   2-D: y = 2*step + cell/16, x = 16*patch + cell%16
+//   1-D: x = 2048*step + 32*patch + cell
+//   brick (layer k, plane b, patch p): bit 32*t + m = bit b of code
+//   (4k+t, p, m); flags of layer k: 16 u64 words, bit p of word b = brick
+//   nonzero; payload of a chunk: nonzero bricks in (k, b, p) order, then the
+//   escape pairs {u32 n, i32 delta} ascending in n, padded to 16 B.
+#pragma once
+#include <stdint.h>
+
+namespace fz {
+
+constexpr uint32_t kMagic = 0x314D5A46u;  // "FZM1"
+constexpr uint16_t kVersion = 1;
+constexpr int kHeaderBytes = 128;
+constexpr int kSteps = 16;
+constexpr int kStepCodes = 2048;
+constexpr int kPatches = 64;
+constexpr int kPatchCodes = 32;
+constexpr int kLayers = 4;
+constexpr int kPlanes = 16;
+constexpr int kChunkCodes = kSteps * kStepCodes;
+constexpr int kFlagBytesPerChunk = kLayers * kPlanes * 8;
+constexpr int kLayerOutlierCap = 256;
+constexpr int kChunkOutlierCap = kLayers * kLayerOutlierCap;
+constexpr uint32_t kEscape = 0x8000u;
+// worst-case payload of one chunk: every brick nonzero plus the escape cap
+constexpr int64_t kChunkPayloadBound = (int64_t)kLayers * kPlanes * kPatches * 16 + kChunkOutlierCap * 8;
+
+// header byte offsets
+constexpr int kOffMagic = 0, kOffVersion = 4, kOffHdrBytes = 6, kOffStatus = 8, kOffDtype = 12, kOffRank = 13,
+              kOffEbMode = 14, kOffDims = 16, kOffEbUser = 40, kOffEbx2 = 48, kOffInv = 52, kOffVmin = 56,
+              kOffVmax = 60, kOffChunk = 64, kOffNChunks = 72, kOffNnz = 80, kOffNout = 88, kOffTotal = 96;
+
+// status bits
+constexpr uint32_t kErrNonfinite = 1u, kErrEbRange = 2u, kErrOutlierCap = 4u;
+
+// scratch (after the worst-case stream) used by one compression
+struct Scratch {
+    uint32_t ticket;      // chunk tickets, in launch order
+    uint32_t pre_status;  // errors found before the main pass (REL params)
+    uint32_t min_key;     // order-preserving keys of the value range
+    uint32_t max_key;
+    uint32_t nonfinite;
+    uint32_t pad[11];
+    // followed by uint64_t state[n_chunks] at byte 64
+};
+constexpr int kScratchStateOff = 64;
+
+// lookback state word: flag in the top 2 bits, value (16-B units) below
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kValueMask = (1ull << 62) - 1;
+
+struct Geom {
+    int rank;
+    int box[3];
+    int64_t n[3];     // slowest-first, trailing unused = 1
+    int64_t grid[3];  // chunks per dimension
+    int64_t n_chunks;
+    int64_t table_off, flags_off, payload_off;  // = header bytes
+    int64_t scratch_off, bound;                 // bound includes the scratch
+};
+
+inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
+{
+    if (rank < 1 || rank > 3) return false;
+    g->rank = rank;
+    for (int i = 0; i < 3; i++) { g->n[i] = 1; g->box[i] = 1; }
+    for (int i = 0; i < rank; i++) {
+        if (dims[i] == 0 || dims[i] > (1ull << 40)) return false;
+        g->n[i] = (int64_t)dims[i];
+    }
+    if (rank == 3) { g->box[0] = 16; g->box[1] = 32; g->box[2] = 64; }
+    if (rank == 2) { g->box[0] = 32; g->box[1] = 1024; }
+    if (rank == 1) { g->box[0] = 32768; }
+    g->n_chunks = 1;
+    for (int i = 0; i < 3; i++) {
+        g->grid[i] = (g->n[i] + g->box[i] - 1) / g->box[i];
+        g->n_chunks *= g->grid[i];
+    }
+    if (g->n_chunks >= (1ll << 31)) return false;
+    int64_t table = (8 * g->n_chunks + 15) / 16 * 16;
+    g->table_off = kHeaderBytes;
+    g->flags_off = kHeaderBytes + table;
+    g->payload_off = g->flags_off + (int64_t)kFlagBytesPerChunk * g->n_chunks;
+    int64_t worst = g->payload_off + g->n_chunks * kChunkPayloadBound;
+    g->scratch_off = (worst + 255) / 256 * 256;
+    g->bound = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
+    return true;
+}
+
+}  // namespace fz

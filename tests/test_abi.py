@@ -1,0 +1,68 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/fz.h declares, sizes agree with the oracle's format
+arithmetic, argument errors return immediately, and the header parser reads
+an oracle-made stream."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2304_12557_amd as fz
+from oracle import oracle as O
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fz_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 6
+    L = fz.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fz.SYMBOLS)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (100, 500, 500), (1800, 3600), (7,), (1, 1, 1), (33, 1, 1025),
+                                   (512, 512, 512), (280953867,)])
+def test_sizes_match_oracle(shape):
+    assert fz.header_bytes(shape) == O.header_bytes(shape)
+    assert fz.compress_bound(shape) >= O.bound(shape)
+
+
+def test_argument_errors_return_immediately():
+    L = fz.lib()
+    d = fz.dims_of((10, 10))
+    assert L.fz_compress(None, ctypes.byref(d), 1e-3, 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), -1.0, 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), float("nan"), 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 7, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-45, 0, ctypes.c_void_p(16), None) == 4
+    bad = fz.FzDims()
+    bad.rank = 4
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(bad), 1e-3, 1, ctypes.c_void_p(16), None) == 1
+    bad.rank = 2
+    bad.n[0], bad.n[1] = 0, 5
+    assert L.fz_compress_bound(ctypes.byref(bad)) == 0
+    assert L.fz_decompress(None, ctypes.c_void_p(16), ctypes.byref(d), None, None) == 1
+    assert fz.lib().fz_strerror(6) == b"malformed stream"
+
+
+def test_stream_info_parses_oracle_header():
+    x = synth.sine_field((20, 40, 70), seed=9)
+    s, st = O.compress(x, 1e-3, O.EB_REL)
+    info = fz.stream_info(s[:128].tobytes())
+    assert info["total_bytes"] == len(s)
+    assert info["rank"] == 3 and info["n"] == [20, 40, 70]
+    assert info["header_bytes"] == O.header_bytes(x.shape)
+    assert info["status"] == st == 0
+    with pytest.raises(fz.FzError):
+        fz.stream_info(b"\0" * 128)

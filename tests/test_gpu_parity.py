@@ -1,0 +1,138 @@
+"""GPU parity: the HIP path against the oracle, through the C ABI.
+
+Streams must be byte-identical and reconstructions bit-identical (the format
+fixes one correct stream per input; the floating-point steps use the same
+fp32 operation order on both sides).  Sizes span several chunks and ragged
+tails; edge cases cover single elements, constant and zero fields, escapes,
+and the data-dependent error bits.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2304_12557_amd as fz
+from oracle import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_compress(x, eb, mode):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    buf = fz.compress(xt, eb, mode="rel" if mode == O.EB_REL else "abs")
+    torch.cuda.synchronize()
+    n = fz.stream_size(buf)
+    return buf, buf[:n].cpu().numpy()
+
+
+def gpu_decompress(buf, shape):
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    y = fz.decompress(buf, shape, err=err)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), int(err.item())
+
+
+def check_case(x, eb, mode=O.EB_REL):
+    print("case", x.shape, eb, mode, flush=True)
+    ref, st = O.compress(x, eb, mode)
+    buf, s = gpu_compress(x, eb, mode)
+    assert st == 0
+    assert s.size == ref.size, (s.size, ref.size)
+    if not np.array_equal(s, ref):
+        diff = np.nonzero(s != ref)[0]
+        raise AssertionError("stream differs at %d bytes, first at %d of %d" % (diff.size, diff[0], s.size))
+    y, err = gpu_decompress(buf, x.shape)
+    assert err == 0
+    yo, erro = O.decompress(ref, x.shape)
+    assert erro == 0
+    assert np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+    return s
+
+
+CASES = [
+    ((64, 64, 64), 0, 1e-3),        # the small 3-D workload
+    ((37, 70, 130), 1, 1e-4),       # ragged 3-D, several chunks per dim
+    ((16, 32, 64), 2, 1e-2),        # exactly one chunk
+    ((17, 33, 65), 3, 1e-3),        # one cell past a chunk in every dim
+    ((75, 2050), 4, 1e-3),          # ragged 2-D
+    ((32, 1024), 5, 1e-4),          # one 2-D chunk
+    ((100000,), 6, 1e-3),           # ragged 1-D
+    ((32768 * 3,), 7, 1e-4),        # whole 1-D chunks
+    ((5, 3, 2), 8, 1e-3), ((1, 1, 1), 9, 1e-3), ((1,), 10, 1e-3), ((3, 7), 11, 1e-3), ((2, 1, 9000), 12, 1e-3),
+]
+
+
+@pytest.mark.parametrize("shape,seed,eb", CASES)
+def test_parity_rel(shape, seed, eb):
+    check_case(synth.sine_field(shape, seed=seed), eb)
+
+
+@pytest.mark.parametrize("shape,seed", [((40, 70, 130), 20), ((70, 2100), 21), ((70001,), 22)])
+def test_parity_abs(shape, seed):
+    check_case(synth.sine_field(shape, seed=seed), 2.5e-4, O.EB_ABS)
+
+
+def test_parity_unaligned_width():
+    # nx not a multiple of 4 exercises the scalar load/store path
+    check_case(synth.sine_field((20, 45, 131), seed=30), 1e-3)
+    check_case(synth.sine_field((45, 1027), seed=31), 1e-3)
+
+
+def test_parity_zero_and_constant_fields():
+    check_case(np.zeros((40, 50, 70), np.float32), 1e-3)
+    check_case(np.full((40, 50, 70), 3.25, np.float32), 1e-3)
+    check_case(np.zeros((100, 1000), np.float32), 1e-3)
+
+
+def test_parity_escapes():
+    x = synth.sine_field((20, 40, 70), seed=2) + np.float32(1000.0)
+    s = check_case(x, 1e-3, O.EB_ABS)
+    assert fz.stream_info(s[:128].tobytes())["n_outliers"] > 0
+    x2 = synth.sine_field((50, 3000), seed=3) + np.float32(500.0)
+    check_case(x2, 1e-3, O.EB_ABS)
+    x1 = synth.sine_field((70000,), seed=4) + np.float32(500.0)
+    check_case(x1, 1e-3, O.EB_ABS)
+
+
+def test_status_bits_match_oracle():
+    x = synth.sine_field((20, 40, 70), seed=1)
+    bad = x.copy()
+    bad[3, 4, 5] = np.nan
+    for mode in (O.EB_REL, O.EB_ABS):
+        _, st = O.compress(bad, 1e-3, mode)
+        buf, _ = gpu_compress(bad, 1e-3, mode)
+        assert fz.stream_info(buf)["status"] == st == O.ERR_NONFINITE
+        _, err = gpu_decompress(buf, bad.shape)
+        assert err == 8
+    big = x * np.float32(1e30)
+    _, st = O.compress(big, 1e-10, O.EB_ABS)
+    buf, _ = gpu_compress(big, 1e-10, O.EB_ABS)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_EB_RANGE
+    rng = np.random.default_rng(3)
+    w = (rng.standard_normal((16, 32, 64)) * 1e6).astype(np.float32)
+    _, st = O.compress(w, 0.5, O.EB_ABS)
+    buf, _ = gpu_compress(w, 0.5, O.EB_ABS)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_OUTLIER_CAP
+
+
+def test_decompress_rejects_bad_stream():
+    x = synth.sine_field((20, 40, 70), seed=5)
+    buf, s = gpu_compress(x, 1e-3, O.EB_REL)
+    bad = buf.clone()
+    bad[0] = 0
+    _, err = gpu_decompress(bad, x.shape)
+    assert err == 6
+    bad = buf.clone()
+    bad[4] = 9
+    _, err = gpu_decompress(bad, x.shape)
+    assert err == 7
+    _, err = gpu_decompress(buf, (20, 40, 71))
+    assert err == 6
+
+
+def test_deterministic_repeats():
+    x = synth.sine_field((48, 96, 200), seed=6)
+    _, a = gpu_compress(x, 1e-4, O.EB_REL)
+    for _ in range(5):
+        _, b = gpu_compress(x, 1e-4, O.EB_REL)
+        assert np.array_equal(a, b)
