@@ -1,17 +1,19 @@
 // fz_compress.hip -- single-pass compression kernel of libfzmi (gfx950).
 //
-// One workgroup (4 waves) per chunk, one wave per layer of 4 steps, one lane
-// per 32-code patch.  Per step a lane: loads its 32 fp32 values, prequantizes
-// them (Sec. 2.3), applies the Lorenzo difference on the integers (Sec. 2.3 /
-// 3.2; the previous step sits in the same lane's registers, the other two
-// neighbours come from adjacent lanes), maps them to sign-magnitude 16-bit
-// codes (Sec. 3.2), and bit-transposes the 32 codes in registers (Sec. 3.3).
+// Persistent workgroups of 4 waves take chunks by ticket.  In a chunk, wave k
+// handles layer k (4 steps), one lane per 32-code patch.  Per step a lane
+// prequantizes its 32 fp32 values (Sec. 2.3), applies the Lorenzo difference
+// on the integers (Sec. 2.3 / 3.2; the previous step sits in the same lane's
+// registers, the other neighbours come from adjacent lanes), maps the deltas
+// to sign-magnitude 16-bit codes (Sec. 3.2) with packed 16-bit arithmetic,
+// and bit-transposes the 32 codes in registers (the bitshuffle of Sec. 3.3).
 // After its 4 steps a lane holds 16 bricks (one per bit plane); a ballot per
-// plane gives the bit flags of the zero-block encoder (Sec. 3.4).  The
-// workgroup then takes its payload offset from a decoupled look-back over
-// the preceding chunks (the device-wide exclusive prefix sum of Sec. 3.4,
-// here without a second kernel) and every lane stores its nonzero bricks
-// with coalesced 16-byte writes.  No intermediate array touches HBM.
+// plane gives the bit flags of the zero-block encoder (Sec. 3.4).  Wave 0
+// then resolves the chunk's payload offset with a decoupled look-back (the
+// device-wide exclusive prefix sum of Sec. 3.4, without a second kernel)
+// while the other waves already load the next chunk, and every lane stores
+// its nonzero bricks with coalesced 16-byte writes.  No intermediate array
+// touches HBM.
 #include <hip/hip_runtime.h>
 
 #include "fz_device.hpp"
@@ -32,7 +34,7 @@ __device__ __forceinline__ void log_escapes(const int (&d)[32], uint32_t (&P)[16
 {
     uint32_t emask = 0;
 #pragma unroll
-    for (int i = 0; i < 32; i++) emask |= (absu(d[i]) > 32767u ? 1u : 0u) << i;
+    for (int i = 0; i < 32; i++) emask |= ((uint32_t)d[i] + 32767u > kEscapeLimit ? 1u : 0u) << i;
     const int cnt = __popc(emask);
     const int incl = wave_incl_scan(cnt, lane);
     const int total = __shfl(incl, 63);
@@ -55,13 +57,30 @@ __device__ __forceinline__ void log_escapes(const int (&d)[32], uint32_t (&P)[16
     log.count += total;
 }
 
-// codes -> escapes -> bit planes, shared tail of every rank's step
-__device__ __forceinline__ void finish_step(const int (&d)[32], uint32_t (&P)[16], EscapeLog& log, uint32_t n0, int lane)
+// codes -> escapes -> bit planes, shared tail of every rank's step.  The fast
+// pass (ESC = false) only reports that a step needs escapes; the layer is then
+// redone by the logging pass (ESC = true), which rewrites those codes.
+template <bool ESC>
+__device__ __forceinline__ bool finish_step(const int (&d)[32], uint32_t (&P)[16], EscapeLog& log, uint32_t n0, int lane)
 {
-    uint32_t macc = 0;
-    pack_codes(d, P, macc);
-    if (__ballot(macc > 32767u)) log_escapes(d, P, log, n0, lane);
+    uint32_t eacc = 0;
+    pack_codes(d, P, eacc);
+    const bool esc = __ballot(eacc > kEscapeLimit) != 0;
+    if (ESC && esc) log_escapes(d, P, log, n0, lane);
     transpose16(P);
+    return esc;
+}
+
+// prequantize 32 values; `facc` tracks max |p| (as shifted bits)
+__device__ __forceinline__ void prequant32(const float (&v)[32], float inv, uint32_t& facc, int (&q)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 32; i += 2) {
+        const float p0 = v[i] * inv, p1 = v[i + 1] * inv;
+        facc = max(facc, max(__float_as_uint(p0) << 1, __float_as_uint(p1) << 1));
+        q[i] = (int)__builtin_rintf(p0);
+        q[i + 1] = (int)__builtin_rintf(p1);
+    }
 }
 
 // ------------------------------------------------------------------ loaders
@@ -71,7 +90,7 @@ __device__ __forceinline__ void load_run(const float* __restrict__ p, float* v)
     if (VEC4) {
 #pragma unroll
         for (int j = 0; j < CNT / 4; j++) {
-            float4 t = *reinterpret_cast<const float4*>(p + 4 * j);
+            const float4 t = *reinterpret_cast<const float4*>(p + 4 * j);
             v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
         }
     } else {
@@ -87,411 +106,494 @@ __device__ __forceinline__ void load_run_masked(const float* __restrict__ p, flo
     for (int j = 0; j < CNT; j++) v[j] = j < valid ? p[j] : 0.0f;
 }
 
-// ------------------------------------------------------------------- 3-D
-// patch: rows y0..y0+3 (ey valid), cols x0..x0+7 (ex valid) of plane z
-template <bool EDGE, bool VEC4>
-__device__ __forceinline__ void load3(const float* __restrict__ x, const Geom& g, int64_t z, int64_t y0, int64_t x0,
-                                      int ey, int ex, float (&v)[32])
+// Per-chunk, per-lane geometry.  step_base() is uniform (scalar); lane
+// offsets inside a step are 32-bit.
+struct Lane {
+    int64_t org[3], ext[3];
+    int L;
+    bool edge;
+    uint32_t off;  // lane offset of its first value inside a step
+    int ev, eh;    // 3-D: valid rows / columns of the patch; 2-D: columns
+};
+
+template <int RANK>
+__device__ __forceinline__ Lane lane_geo(const Geom& g, int64_t c, int lane)
 {
+    Lane l;
+    chunk_box(g, c, l.org, l.ext);
+    l.L = layers_of(RANK, l.ext[0]);
+    l.edge = false;
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const float* p = x + ((z * g.n[1] + y0 + r) * g.n[2] + x0);
+    for (int i = 0; i < 3; i++) l.edge |= l.ext[i] < g.box[i];
+    if (RANK == 3) {
+        const int py = lane & 7, px = lane >> 3;
+        l.off = (uint32_t)(4 * py * g.n[2] + 8 * px);
+        l.ev = clampi(l.ext[1] - 4 * py, 0, 4);
+        l.eh = clampi(l.ext[2] - 8 * px, 0, 8);
+    } else if (RANK == 2) {
+        l.off = (uint32_t)(16 * lane);
+        l.ev = 2;
+        l.eh = clampi(l.ext[1] - 16 * lane, 0, 16);
+    } else {
+        l.off = (uint32_t)(kPatchCodes * lane);
+        l.ev = 1;
+        l.eh = 32;
+    }
+    return l;
+}
+
+// first value of step s (3-D: plane s; 2-D: row 2s; 1-D: value 2048 s) of the chunk
+template <int RANK>
+__device__ __forceinline__ const float* step_base(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s)
+{
+    if (RANK == 3) return x + ((l.org[0] + s) * g.n[1] + l.org[1]) * g.n[2] + l.org[2];
+    if (RANK == 2) return x + (l.org[0] + 2 * s) * g.n[1] + l.org[1];
+    return x + l.org[0] + (int64_t)kStepCodes * s;
+}
+
+// load the lane's 32 values of step s (s = 4k-1 is the halo of layer k).
+// In a chunk cut by the field's edge every index is clamped into the field:
+// cells outside it then hold some in-field value, and their deltas are zeroed
+// later (a delta inside the field never looks at a cell outside it).
+template <int RANK, bool EDGE, bool VEC4>
+__device__ __forceinline__ void load_step(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s, int lane,
+                                          float (&v)[32])
+{
+    const float* b = step_base<RANK>(x, g, l, s);
+    if (RANK == 3) {
+        const int64_t nx = g.n[2];
         if (EDGE) {
-            if (r < ey) load_run_masked<8>(p, v + 8 * r, ex);
-            else
+            const int py = lane & 7, px = lane >> 3;
+            const int ey = (int)l.ext[1] - 1, ex = (int)l.ext[2] - 1;
 #pragma unroll
-                for (int j = 0; j < 8; j++) v[8 * r + j] = 0.0f;
+            for (int r = 0; r < 4; r++) {
+                const float* p = b + (uint32_t)min(4 * py + r, ey) * (uint32_t)nx;
+#pragma unroll
+                for (int c = 0; c < 8; c++) v[8 * r + c] = p[min(8 * px + c, ex)];
+            }
         } else {
-            load_run<8, VEC4>(p, v + 8 * r);
+#pragma unroll
+            for (int r = 0; r < 4; r++) load_run<8, VEC4>(b + l.off + r * nx, v + 8 * r);
+        }
+    } else if (RANK == 2) {
+        const int64_t nx = g.n[1];
+        if (EDGE) {
+            const int ex = (int)l.ext[1] - 1;
+            const int64_t last = l.ext[0] - 1 - 2 * s;  // last field row relative to the step
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const float* p = b + (r < last ? r : last) * nx;
+#pragma unroll
+                for (int c = 0; c < 16; c++) v[16 * r + c] = p[min(16 * lane + c, ex)];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 2; r++) load_run<16, VEC4>(b + l.off + r * nx, v + 16 * r);
+        }
+    } else {
+        if (EDGE) {
+            const int64_t last = l.ext[0] - 1 - (int64_t)kStepCodes * s;
+#pragma unroll
+            for (int m = 0; m < 32; m++) {
+                const int64_t i = (int64_t)l.off + m;
+                v[m] = b[i < last ? i : last];
+            }
+        } else {
+            load_run<32, VEC4>(b + l.off, v);
         }
     }
 }
 
-template <bool EDGE, bool VEC4>
-__device__ __forceinline__ void layer3(const float* __restrict__ x, const Geom& g, const int64_t (&org)[3],
-                                       const int64_t (&ext)[3], int k, float inv, int lane, uint32_t (&W)[16][4],
-                                       uint32_t& facc, EscapeLog& log)
+// ------------------------------------------------------------- one layer
+// `h` holds the halo (3-D: the plane before the layer; 2-D: the two rows
+// before it, of which the second is used; 1-D: unused) and `v` the first
+// step, both loaded ahead of time.  The plane-b word of step t goes to
+// Wl[(b * 4 + t) * 64 + lane] in LDS (brick (k, b, lane) = its 4 words) and
+// nz[b] collects their OR for the flags.
+// Returns whether some delta of the layer needs an escape (only the ESC pass
+// logs them).
+template <int RANK, bool EDGE, bool VEC4, bool ESC>
+__device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
+                                      int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
+                                      uint32_t& facc, EscapeLog& log)
 {
+    // the logging pass (ESC) keeps one copy of the step code: it runs rarely
+    // and must not add to the register budget of the fast pass
+    bool esc = false;
+#pragma unroll
+    for (int b = 0; b < 16; b++) nz[b] = 0u;
     const int py = lane & 7, px = lane >> 3;
-    const int64_t y0 = org[1] + 4 * py, x0 = org[2] + 8 * px;
-    const int ey = EDGE ? clampi(ext[1] - 4 * py, 0, 4) : 4;
-    const int ex = EDGE ? clampi(ext[2] - 8 * px, 0, 8) : 8;
+    // previous-step state: 3-D plane (32), 2-D row (16), 1-D last value (uniform)
     int qprev[32];
-    if (k == 0) {
+    int carry1 = 0;
+    if (k == 0 || RANK == 1) {
 #pragma unroll
         for (int i = 0; i < 32; i++) qprev[i] = 0;
-    } else {  // halo: the plane just before this layer, same chunk
-        float h[32];
-        load3<EDGE, VEC4>(x, g, org[0] + 4 * k - 1, y0, x0, ey, ex, h);
-#pragma unroll
-        for (int i = 0; i < 32; i++) qprev[i] = prequant(h[i], inv, facc);
-    }
-    float v[32];
-    load3<EDGE, VEC4>(x, g, org[0] + 4 * k, y0, x0, ey, ex, v);
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        const int s = 4 * k + t;
-        if (s >= ext[0]) {
-#pragma unroll
-            for (int b = 0; b < 16; b++) W[b][t] = 0u;
-            continue;
+        if (RANK == 1 && k > 0) {
+            uint32_t dummy = 0;
+            carry1 = prequant(x[l.org[0] + (int64_t)kStepCodes * 4 * k - 1], inv, dummy);
         }
-        float vn[32];
-        if (t < 3 && s + 1 < ext[0]) load3<EDGE, VEC4>(x, g, org[0] + s + 1, y0, x0, ey, ex, vn);
-        int a[32];
-#pragma unroll
-        for (int i = 0; i < 32; i++) {
-            const int q = prequant(v[i], inv, facc);
-            a[i] = q - qprev[i];  // Dz
-            qprev[i] = q;
-        }
-        int b[32];
-#pragma unroll
-        for (int c = 0; c < 8; c++) b[c] = a[c] - shift_up1(py == 7 ? 0 : a[24 + c], lane);  // Dy, row above from lane-1
-#pragma unroll
-        for (int r = 1; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < 8; c++) b[8 * r + c] = a[8 * r + c] - a[8 * (r - 1) + c];
-        int d[32];
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int left = lane_value(b[8 * r + 7], lane - 8);  // Dx, column to the left from lane-8
-            d[8 * r] = b[8 * r] - (px == 0 ? 0 : left);
-#pragma unroll
-            for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
-        }
-        if (EDGE) {
-#pragma unroll
-            for (int r = 0; r < 4; r++)
-#pragma unroll
-                for (int c = 0; c < 8; c++)
-                    if (!(r < ey && c < ex)) d[8 * r + c] = 0;
-        }
-        uint32_t P[16];
-        finish_step(d, P, log, (uint32_t)s * kStepCodes, lane);
-#pragma unroll
-        for (int bb = 0; bb < 16; bb++) W[bb][t] = P[bb];
-#pragma unroll
-        for (int i = 0; i < 32; i++) v[i] = vn[i];
-    }
-}
-
-// ------------------------------------------------------------------- 2-D
-template <bool EDGE, bool VEC4>
-__device__ __forceinline__ void load2(const float* __restrict__ x, const Geom& g, int64_t y, int64_t x0, int ry, int ex,
-                                      float* v)
-{
-    // one row of 16 values; ry = 1 if the row is inside the field
-    const float* p = x + (y * g.n[1] + x0);
-    if (EDGE) {
-        if (ry) load_run_masked<16>(p, v, ex);
-        else
-#pragma unroll
-            for (int j = 0; j < 16; j++) v[j] = 0.0f;
+    } else if (RANK == 3) {
+        prequant32(h, inv, facc, qprev);
     } else {
-        load_run<16, VEC4>(p, v);
-    }
-}
-
-template <bool EDGE, bool VEC4>
-__device__ __forceinline__ void layer2(const float* __restrict__ x, const Geom& g, const int64_t (&org)[3],
-                                       const int64_t (&ext)[3], int k, float inv, int lane, uint32_t (&W)[16][4],
-                                       uint32_t& facc, EscapeLog& log)
-{
-    const int64_t x0 = org[1] + 16 * lane;
-    const int ex = EDGE ? clampi(ext[1] - 16 * lane, 0, 16) : 16;
-    int qprev[16];
-    if (k == 0) {
+        int qh[32];
+        prequant32(h, inv, facc, qh);
 #pragma unroll
-        for (int i = 0; i < 16; i++) qprev[i] = 0;
-    } else {  // halo: the row just before this layer
-        float h[16];
-        load2<EDGE, VEC4>(x, g, org[0] + 8 * k - 1, x0, 1, ex, h);
-#pragma unroll
-        for (int i = 0; i < 16; i++) qprev[i] = prequant(h[i], inv, facc);
+        for (int c = 0; c < 16; c++) qprev[c] = qh[16 + c];
     }
-    float v[32];
-    {
-        const int64_t yr = 8 * k;
-        load2<EDGE, VEC4>(x, g, org[0] + yr, x0, yr < ext[0], ex, v);
-        load2<EDGE, VEC4>(x, g, org[0] + yr + 1, x0, yr + 1 < ext[0], ex, v + 16);
-    }
-#pragma unroll
+#pragma unroll(ESC ? 1 : 4)
     for (int t = 0; t < 4; t++) {
         const int s = 4 * k + t;
-        if (2 * s >= ext[0]) {
+        if (EDGE) {
+            const int64_t lo = RANK == 3 ? s : RANK == 2 ? 2 * s : (int64_t)kStepCodes * s;
+            if (lo >= l.ext[0]) {
 #pragma unroll
-            for (int b = 0; b < 16; b++) W[b][t] = 0u;
-            continue;
+                for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] = 0u;
+                continue;
+            }
         }
         float vn[32];
-        if (t < 3 && 2 * (s + 1) < ext[0]) {
-            load2<EDGE, VEC4>(x, g, org[0] + 2 * (s + 1), x0, 1, ex, vn);
-            load2<EDGE, VEC4>(x, g, org[0] + 2 * (s + 1) + 1, x0, 2 * (s + 1) + 1 < ext[0], ex, vn + 16);
+        if (t < 3) {
+            bool next = true;
+            if (EDGE) {
+                const int64_t lo = RANK == 3 ? s + 1 : RANK == 2 ? 2 * (s + 1) : (int64_t)kStepCodes * (s + 1);
+                next = lo < l.ext[0];
+            }
+            if (next) load_step<RANK, EDGE, VEC4>(x, g, l, s + 1, lane, vn);
         }
         int q[32];
-#pragma unroll
-        for (int i = 0; i < 32; i++) q[i] = prequant(v[i], inv, facc);
-        int b[32];
-#pragma unroll
-        for (int c = 0; c < 16; c++) {
-            b[c] = q[c] - qprev[c];          // Dy against the previous row (same lane)
-            b[16 + c] = q[16 + c] - q[c];
-            qprev[c] = q[16 + c];
-        }
+        prequant32(v, inv, facc, q);
         int d[32];
+        if (RANK == 3) {
+            int a[32];
 #pragma unroll
-        for (int r = 0; r < 2; r++) {
-            d[16 * r] = b[16 * r] - shift_up1(b[16 * r + 15], lane);  // Dx, left column from lane-1 (0 at lane 0)
+            for (int i = 0; i < 32; i++) {
+                a[i] = q[i] - qprev[i];  // Dz
+                qprev[i] = q[i];
+            }
+            int b[32];
 #pragma unroll
-            for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
-        }
-        if (EDGE) {
-            const bool r1 = 2 * s + 1 < ext[0];
+            for (int c = 0; c < 8; c++) {  // Dy; row 0 takes row 3 of lane-1 (0 for py == 0)
+                const int up = shift_up1_raw(a[24 + c]);
+                b[c] = a[c] - (py == 0 ? 0 : up);
+            }
 #pragma unroll
-            for (int c = 0; c < 16; c++) {
-                if (!(c < ex)) d[c] = 0;
-                if (!(c < ex && r1)) d[16 + c] = 0;
+            for (int r = 1; r < 4; r++)
+#pragma unroll
+                for (int c = 0; c < 8; c++) b[8 * r + c] = a[8 * r + c] - a[8 * (r - 1) + c];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {  // Dx; column 0 takes column 7 of lane-8 (0 for px == 0)
+                const int left = lane_value(b[8 * r + 7], lane - 8);
+                d[8 * r] = b[8 * r] - (px == 0 ? 0 : left);
+#pragma unroll
+                for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
+            }
+            if (EDGE) {
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int c = 0; c < 8; c++)
+                        if (!(r < l.ev && c < l.eh)) d[8 * r + c] = 0;
+            }
+        } else if (RANK == 2) {
+            int b[32];
+#pragma unroll
+            for (int c = 0; c < 16; c++) {  // Dy against the previous row of the same lane
+                b[c] = q[c] - qprev[c];
+                b[16 + c] = q[16 + c] - q[c];
+                qprev[c] = q[16 + c];
+            }
+#pragma unroll
+            for (int r = 0; r < 2; r++) {  // Dx; column 0 takes column 15 of lane-1 (0 at lane 0)
+                const int left = shift_up1_raw(b[16 * r + 15]);
+                d[16 * r] = b[16 * r] - (lane == 0 ? 0 : left);
+#pragma unroll
+                for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
+            }
+            if (EDGE) {
+                const bool r1 = 2 * s + 1 < l.ext[0];
+#pragma unroll
+                for (int c = 0; c < 16; c++) {
+                    if (!(c < l.eh)) d[c] = 0;
+                    if (!(c < l.eh && r1)) d[16 + c] = 0;
+                }
+            }
+        } else {
+            const int left = shift_up1_raw(q[31]);
+            d[0] = q[0] - (lane == 0 ? carry1 : left);
+#pragma unroll
+            for (int m = 1; m < 32; m++) d[m] = q[m] - q[m - 1];
+            carry1 = __builtin_amdgcn_readlane(q[31], 63);
+            if (EDGE) {
+                const int valid = clampi(l.ext[0] - ((int64_t)kStepCodes * s + l.off), 0, 32);
+#pragma unroll
+                for (int m = 0; m < 32; m++)
+                    if (!(m < valid)) d[m] = 0;
             }
         }
         uint32_t P[16];
-        finish_step(d, P, log, (uint32_t)s * kStepCodes, lane);
+        esc |= finish_step<ESC>(d, P, log, (uint32_t)s * kStepCodes, lane);
 #pragma unroll
-        for (int bb = 0; bb < 16; bb++) W[bb][t] = P[bb];
+        for (int bb = 0; bb < 16; bb++) {
+            Wl[(bb * 4 + t) * 64 + lane] = P[bb];
+            nz[bb] |= P[bb];
+        }
+        if (t < 3) {
 #pragma unroll
-        for (int i = 0; i < 32; i++) v[i] = vn[i];
+            for (int i = 0; i < 32; i++) v[i] = vn[i];
+        }
+    }
+    return esc;
+}
+
+// Load the halo and the first step of layer k of a chunk ahead of time.
+template <int RANK, bool VEC4>
+__device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom& g, const Lane& l, int k, int lane,
+                                         float (&h)[32], float (&v)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 32; i++) {  // every path defines both, so no old value stays live
+        h[i] = 0.0f;
+        v[i] = 0.0f;
+    }
+    if (k >= l.L) return;
+    if (l.edge) {
+        if (k > 0 && RANK != 1) load_step<RANK, true, VEC4>(x, g, l, 4 * k - 1, lane, h);
+        load_step<RANK, true, VEC4>(x, g, l, 4 * k, lane, v);
+    } else {
+        if (k > 0 && RANK != 1) load_step<RANK, false, VEC4>(x, g, l, 4 * k - 1, lane, h);
+        load_step<RANK, false, VEC4>(x, g, l, 4 * k, lane, v);
     }
 }
 
-// ------------------------------------------------------------------- 1-D
-template <bool EDGE, bool VEC4>
-__device__ __forceinline__ void layer1(const float* __restrict__ x, const Geom& g, const int64_t (&org)[3],
-                                       const int64_t (&ext)[3], int k, float inv, int lane, uint32_t (&W)[16][4],
-                                       uint32_t& facc, EscapeLog& log)
+// Out-of-line layer pass for the uncommon cases: a chunk cut by the field's
+// edge, or a layer whose deltas need escapes (computed again with logging).
+// It loads its own inputs, writes the layer's bricks to Wl and returns
+// (escape count << 32) | max-|p| bits.  The geometry is read from the copy
+// in the scratch so that nothing large crosses the call.
+template <int RANK, bool VEC4>
+__device__ __forceinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
+                                            int64_t c, int k, float inv, int lane, uint32_t* Wl, uint32_t* oidx,
+                                            int32_t* oval)
 {
-    int carry = 0;  // q just before the current step (uniform)
-    if (k > 0) {
-        uint32_t dummy = 0;
-        carry = prequant(x[org[0] + 8192 * k - 1], inv, dummy);
-    }
-    auto valid_of = [&](int s) -> int {
-        return EDGE ? clampi(ext[0] - ((int64_t)kStepCodes * s + kPatchCodes * lane), 0, 32) : 32;
-    };
-    float v[32];
-    {
-        const int s = 4 * k;
-        const float* p = x + org[0] + (int64_t)kStepCodes * s + kPatchCodes * lane;
-        if (EDGE) load_run_masked<32>(p, v, valid_of(s));
-        else load_run<32, VEC4>(p, v);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        const int s = 4 * k + t;
-        if ((int64_t)kStepCodes * s >= ext[0]) {
-#pragma unroll
-            for (int b = 0; b < 16; b++) W[b][t] = 0u;
-            continue;
-        }
-        float vn[32];
-        if (t < 3 && (int64_t)kStepCodes * (s + 1) < ext[0]) {
-            const float* p = x + org[0] + (int64_t)kStepCodes * (s + 1) + kPatchCodes * lane;
-            if (EDGE) load_run_masked<32>(p, vn, valid_of(s + 1));
-            else load_run<32, VEC4>(p, vn);
-        }
-        int q[32];
-#pragma unroll
-        for (int i = 0; i < 32; i++) q[i] = prequant(v[i], inv, facc);
-        int d[32];
-        const int left = shift_up1(q[31], lane);
-        d[0] = q[0] - (lane == 0 ? carry : left);
-#pragma unroll
-        for (int m = 1; m < 32; m++) d[m] = q[m] - q[m - 1];
-        carry = __builtin_amdgcn_readlane(q[31], 63);
-        if (EDGE) {
-            const int valid = valid_of(s);
-#pragma unroll
-            for (int m = 0; m < 32; m++)
-                if (!(m < valid)) d[m] = 0;
-        }
-        uint32_t P[16];
-        finish_step(d, P, log, (uint32_t)s * kStepCodes, lane);
-#pragma unroll
-        for (int bb = 0; bb < 16; bb++) W[bb][t] = P[bb];
-#pragma unroll
-        for (int i = 0; i < 32; i++) v[i] = vn[i];
-    }
+    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
+    const Lane l = lane_geo<RANK>(g, c, lane);
+    float h[32], v[32];
+    prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
+    uint32_t nz[16], facc = 0;
+    EscapeLog log{oidx, oval, 0};
+    if (l.edge) layer<RANK, true, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    else layer<RANK, false, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    return ((uint64_t)(uint32_t)log.count << 32) | facc;
 }
 
 // Rare path: a step saw NaN/Inf or |x*inv| >= 2^31.  Re-read the layer's
-// cells and classify them the way the format defines the status bits.
-__device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const Geom& g, const int64_t (&org)[3],
-                                                 const int64_t (&ext)[3], int k, float inv, int lane)
+// cells and classify them the way the format defines the status bits
+// (halo values belong to the previous layer, which reports them).
+__device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
+                                                 int64_t c, int k, float inv, int lane)
 {
+    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
+    int64_t o[3], e[3];
+    chunk_box(g, c, o, e);
     uint32_t err = 0;
     for (int t = 0; t < 4; t++) {
         const int s = 4 * k + t;
         for (int m = 0; m < 32; m++) {
-            int64_t r[3] = {0, 0, 0};
-            if (g.rank == 3) { r[0] = s; r[1] = 4 * (lane % 8) + m / 8; r[2] = 8 * (lane / 8) + m % 8; }
-            else if (g.rank == 2) { r[0] = 2 * s + m / 16; r[1] = 16 * lane + m % 16; }
-            else { r[0] = (int64_t)kStepCodes * s + kPatchCodes * lane + m; }
-            if (r[0] >= ext[0] || r[1] >= ext[1] || r[2] >= ext[2]) continue;
-            const float v = x[((org[0] + r[0]) * g.n[1] + org[1] + r[1]) * g.n[2] + org[2] + r[2]];
+            int64_t r0 = 0, r1 = 0, r2 = 0;
+            if (g.rank == 3) { r0 = s; r1 = 4 * (lane % 8) + m / 8; r2 = 8 * (lane / 8) + m % 8; }
+            else if (g.rank == 2) { r0 = 2 * s + m / 16; r1 = 16 * lane + m % 16; }
+            else { r0 = (int64_t)kStepCodes * s + kPatchCodes * lane + m; }
+            if (r0 >= e[0] || r1 >= e[1] || r2 >= e[2]) continue;
+            const float v = x[((o[0] + r0) * g.n[1] + o[1] + r1) * g.n[2] + o[2] + r2];
             if (!__builtin_isfinite(v)) err |= kErrNonfinite;
             else if (!(__builtin_fabsf(v * inv) < 2147483648.0f)) err |= kErrEbRange;
         }
     }
-    return err;  // halo values belong to the previous layer, which reports them
+    return err;
 }
 
-// Decoupled look-back (single-pass exclusive prefix sum over chunks): publish
-// this chunk's aggregate, walk back accumulating aggregates until a chunk with
-// a published inclusive prefix, then publish ours.  Tickets are taken in
-// order, so every chunk waited on has a running or finished workgroup.
-__device__ uint64_t lookback(uint64_t* state, int64_t c, uint64_t agg)
+// Decoupled look-back (single-pass exclusive prefix sum over chunks), run by
+// one whole wave: publish this chunk's aggregate, then read the states of the
+// 64 preceding chunks at once.  If every chunk up to the nearest one with a
+// published inclusive prefix has at least its aggregate, the exclusive prefix
+// is their sum; without an inclusive prefix in the window, the window slides
+// back by 64.  Tickets are taken in order, so every chunk waited on belongs to
+// a running workgroup that publishes its aggregate before it waits itself.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 {
-    if (c == 0) {
-        __hip_atomic_store(&state[0], kFlagIncl | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, sh);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), sh);
+        v += ((uint64_t)hi << 32) | lo;
     }
-    __hip_atomic_store(&state[c], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lookback(uint64_t* state, int64_t c, uint64_t agg, int lane)
+{
+    if (lane == 0)
+        __hip_atomic_store(&state[c], (c == 0 ? kFlagIncl : kFlagAgg) | agg, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (c == 0) return 0;
     uint64_t excl = 0;
-    int64_t j = c - 1;
+    int64_t top = c - 1;
     for (;;) {
-        const uint64_t v = __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t j = top - lane;
+        const uint64_t v = j >= 0 ? __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : kFlagIncl;  // before chunk 0: inclusive prefix 0
         const uint64_t f = v & ~kValueMask;
-        if (f == 0) {
-            __builtin_amdgcn_s_sleep(1);
+        const uint64_t incl = __ballot(f == kFlagIncl);
+        const uint64_t notready = __ballot(f == 0);
+        const int first = incl ? __builtin_ctzll(incl) : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notready & need) {
+            __builtin_amdgcn_s_sleep(2);
             continue;
         }
-        excl += v & kValueMask;
-        if (f == kFlagIncl) break;
-        j--;
+        excl += wave_sum64(lane <= first ? (v & kValueMask) : 0ull);
+        if (first < 64) break;
+        top -= 64;
     }
-    __hip_atomic_store(&state[c], kFlagIncl | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+        __hip_atomic_store(&state[c], kFlagIncl | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return excl;
-}
-
-template <int RANK, bool EDGE, bool VEC4>
-__device__ __forceinline__ void run_layer(const float* __restrict__ x, const Geom& g, const int64_t (&org)[3],
-                                          const int64_t (&ext)[3], int k, float inv, int lane, uint32_t (&W)[16][4],
-                                          uint32_t& facc, EscapeLog& log)
-{
-    if (RANK == 3) layer3<EDGE, VEC4>(x, g, org, ext, k, inv, lane, W, facc, log);
-    else if (RANK == 2) layer2<EDGE, VEC4>(x, g, org, ext, k, inv, lane, W, facc, log);
-    else layer1<EDGE, VEC4>(x, g, org, ext, k, inv, lane, W, facc, log);
 }
 
 template <int RANK, bool VEC4>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
 {
-    __shared__ uint32_t s_chunk, s_err;
+    __shared__ uint32_t s_err;
     __shared__ uint32_t s_nnz[kLayers], s_nout[kLayers];
-    __shared__ uint64_t s_off;
+    __shared__ uint64_t s_off, s_chunk;
     __shared__ uint32_t s_oidx[kLayers][kLayerOutlierCap];
     __shared__ int32_t s_oval[kLayers][kLayerOutlierCap];
+    __shared__ uint32_t s_w[kLayers][kPlanes * 4 * 64];  // bricks of each wave's layer
 
     Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
     uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keep it scalar
     if (scr->pre_status) return;  // set before this launch: uniform across the grid
+    const float inv = *reinterpret_cast<const float*>(out + kOffInv);
 
     if (threadIdx.x == 0) {
         s_chunk = atomicAdd(&scr->ticket, 1u);
         s_err = 0;
     }
     __syncthreads();
-    const int64_t c = s_chunk;
-    const float inv = *reinterpret_cast<const float*>(out + kOffInv);
-    int64_t org[3], ext[3];
-    chunk_box(g, c, org, ext);
-    const int L = layers_of(RANK, ext[0]);
-    bool edge = false;
-#pragma unroll
-    for (int i = 0; i < 3; i++) edge |= ext[i] < g.box[i];
+    int64_t c = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_chunk);
+    if (c >= g.n_chunks) return;
+    float h[32], v[32];
+    Lane l = lane_geo<RANK>(g, c, lane);
+    if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
 
-    uint32_t W[16][4];
-    uint32_t facc = 0;
-    EscapeLog log{s_oidx[wave], s_oval[wave], 0};
-    if (wave < L) {
-        if (edge) run_layer<RANK, true, VEC4>(x, g, org, ext, wave, inv, lane, W, facc, log);
-        else run_layer<RANK, false, VEC4>(x, g, org, ext, wave, inv, lane, W, facc, log);
-    } else {
+    for (;;) {
+        uint32_t nz[16];
+        uint32_t facc = 0;
+        uint32_t* Wl = s_w[wave];
+        EscapeLog log{s_oidx[wave], s_oval[wave], 0};
+        if (wave < l.L) {
+            bool slow = l.edge;
+            if (!slow) slow = layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+            if (slow) {  // edge chunk, or escapes to log
+                const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx,
+                                                          log.val);
+                log.count = (int)(r >> 32);
+                facc = max(facc, (uint32_t)r);
 #pragma unroll
-        for (int b = 0; b < 16; b++)
+                for (int b = 0; b < 16; b++)
+                    nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
+                            Wl[(b * 4 + 3) * 64 + lane];
+            }
+        } else {
 #pragma unroll
-            for (int t = 0; t < 4; t++) W[b][t] = 0u;
-    }
-    uint32_t err = 0;
-    if (__ballot(facc >= kPrequantLimit)) {
-        err = classify_errors(x, g, org, ext, wave, inv, lane);
+            for (int b = 0; b < 16; b++) nz[b] = 0u;
+        }
+        uint32_t err = 0;
+        if (__ballot(facc >= kPrequantLimit)) {
+            err = classify_errors(x, out, g.scratch_off, c, wave, inv, lane);
 #pragma unroll
-        for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
-    }
-    if (log.count > kLayerOutlierCap) err |= kErrOutlierCap;
-    const int nout = log.count < kLayerOutlierCap ? log.count : kLayerOutlierCap;
+            for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
+        }
+        if (log.count > kLayerOutlierCap) err |= kErrOutlierCap;
+        const int nout = log.count < kLayerOutlierCap ? log.count : kLayerOutlierCap;
 
-    // flags of the zero-block encoder: one ballot per bit plane
-    uint64_t F[16];
-    uint32_t nnz = 0;
-    uint64_t myflag = 0;
+        // flags of the zero-block encoder: one ballot per bit plane
+        uint64_t F[16];
+        uint32_t nnz = 0;
+        uint64_t myflag = 0;
 #pragma unroll
-    for (int b = 0; b < 16; b++) {
-        F[b] = __ballot((W[b][0] | W[b][1] | W[b][2] | W[b][3]) != 0u);
-        nnz += __popcll(F[b]);
-        myflag = lane == b ? F[b] : myflag;
-    }
-    if (lane < 16)
-        reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
-    if (lane == 0) {
-        s_nnz[wave] = nnz;
-        s_nout[wave] = (uint32_t)nout;
-        if (err) atomicOr(&s_err, err);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+        for (int b = 0; b < 16; b++) {
+            F[b] = __ballot(nz[b] != 0u);
+            nnz += __popcll(F[b]);
+            myflag = lane == b ? F[b] : myflag;
+        }
+        if (lane < 16)
+            reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
+        if (lane == 0) {
+            s_nnz[wave] = nnz;
+            s_nout[wave] = (uint32_t)nout;
+            if (err) atomicOr(&s_err, err);
+        }
+        if (threadIdx.x == 0) s_chunk = atomicAdd(&scr->ticket, 1u);  // next chunk
+        __syncthreads();
+        const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_chunk);
+        if (cn < g.n_chunks) {  // start loading the next chunk while this one is placed
+            l = lane_geo<RANK>(g, cn, lane);
+            if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
+        }
         const uint32_t tn = s_nnz[0] + s_nnz[1] + s_nnz[2] + s_nnz[3];
-        const uint32_t to = s_nout[0] + s_nout[1] + s_nout[2] + s_nout[3];
-        const uint64_t units = tn + (to + 1) / 2;
-        const uint64_t excl = lookback(state, c, units);
-        s_off = excl;
-        uint32_t* tab = reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c);
-        tab[0] = (uint32_t)excl;
-        tab[1] = to;
-        atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
-        atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
-        if (s_err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), s_err);
-        if (c == g.n_chunks - 1)
-            *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (excl + units);
-        // payload is followed by the chunk's escape pairs, padded to 16 B
-        if (to & 1u) {
-            uint8_t* pairs = out + g.payload_off + 16 * (excl + tn);
-            *reinterpret_cast<uint2*>(pairs + 8 * to) = make_uint2(0u, 0u);
+        if (wave == 0) {
+            const uint32_t to = s_nout[0] + s_nout[1] + s_nout[2] + s_nout[3];
+            const uint64_t units = tn + (to + 1) / 2;
+            const uint64_t excl = lookback(state, c, units, lane);
+            if (lane == 0) {
+                s_off = excl;
+                uint32_t* tab = reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c);
+                tab[0] = (uint32_t)excl;
+                tab[1] = to;
+                atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
+                atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
+                if (s_err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), s_err);
+                s_err = 0;
+                if (c == g.n_chunks - 1)
+                    *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (excl + units);
+                if (to & 1u) {  // escape pairs are padded to 16 bytes with a zero pair
+                    uint8_t* pairs = out + g.payload_off + 16 * (excl + tn);
+                    *reinterpret_cast<uint2*>(pairs + 8 * to) = make_uint2(0u, 0u);
+                }
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // compaction: nonzero bricks in (layer, plane, patch) order
-    uint64_t base = s_off;
-    for (int w = 0; w < wave; w++) base += s_nnz[w];
-    uint8_t* pay = out + g.payload_off;
+        // compaction: nonzero bricks in (layer, plane, patch) order
+        uint64_t base = s_off;
+        for (int w = 0; w < wave; w++) base += s_nnz[w];
+        uint8_t* pay = out + g.payload_off;
 #pragma unroll
-    for (int b = 0; b < 16; b++) {
-        if ((F[b] >> lane) & 1ull) {
-            const uint64_t pos = base + mbcnt(F[b]);
-            *reinterpret_cast<uint4*>(pay + 16 * pos) = make_uint4(W[b][0], W[b][1], W[b][2], W[b][3]);
+        for (int b = 0; b < 16; b++) {
+            if (F[b] == 0) continue;  // uniform: a bit plane without nonzero bricks
+            if ((F[b] >> lane) & 1ull) {
+                const uint64_t pos = base + mbcnt(F[b]);
+                const uint32_t* w = Wl + b * 4 * 64 + lane;
+                *reinterpret_cast<uint4*>(pay + 16 * pos) = make_uint4(w[0], w[64], w[128], w[192]);
+            }
+            base += __popcll(F[b]);
         }
-        base += __popcll(F[b]);
-    }
-    if (nout) {
-        const uint32_t tn = s_nnz[0] + s_nnz[1] + s_nnz[2] + s_nnz[3];
-        uint32_t first = 0;
-        for (int w = 0; w < wave; w++) first += s_nout[w];
-        uint32_t* pairs = reinterpret_cast<uint32_t*>(pay + 16 * (s_off + tn));
-        for (int i = lane; i < nout; i += 64) {
-            pairs[2 * (first + i)] = s_oidx[wave][i];
-            pairs[2 * (first + i) + 1] = (uint32_t)s_oval[wave][i];
+        if (nout) {
+            uint32_t first = 0;
+            for (int w = 0; w < wave; w++) first += s_nout[w];
+            uint32_t* pairs = reinterpret_cast<uint32_t*>(pay + 16 * (s_off + tn));
+            for (int i = lane; i < nout; i += 64) {
+                pairs[2 * (first + i)] = s_oidx[wave][i];
+                pairs[2 * (first + i) + 1] = (uint32_t)s_oval[wave][i];
+            }
         }
+        if (cn >= g.n_chunks) break;
+        c = cn;
+        __syncthreads();  // the LDS counts and logs are reused by the next chunk
     }
 }
 
@@ -503,42 +605,47 @@ __global__ void k_init(uint8_t* __restrict__ out, Geom g, HeaderImage h)
     if (tid == 0 && (g.n_chunks & 1))  // the chunk table is padded to 16 bytes with zeros
         *reinterpret_cast<uint2*>(out + g.table_off + 8 * g.n_chunks) = make_uint2(0u, 0u);
     uint32_t* scr = reinterpret_cast<uint32_t*>(out + g.scratch_off);
-    if (tid < kScratchStateOff / 4) {
-        uint32_t v = 0;
-        if (tid == 2) v = 0xFFFFFFFFu;  // min_key
-        scr[tid] = v;
-    }
+    if (tid < kScratchGeomOff / 4) scr[tid] = 0u;
+    static_assert(sizeof(Geom) % 4 == 0 && kScratchGeomOff + sizeof(Geom) <= kScratchStateOff, "scratch layout");
+    if (tid < (int64_t)(sizeof(Geom) / 4))
+        scr[kScratchGeomOff / 4 + tid] = reinterpret_cast<const uint32_t*>(&g)[tid];
     uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
     for (int64_t i = tid; i < g.n_chunks; i += (int64_t)gridDim.x * blockDim.x) state[i] = 0;
 }
 
+// Value range for the relative error bound, two passes without contended
+// atomics: every block writes its partial (min key, max key, non-finite) to
+// the scratch, then k_params folds the partials.  The blocks walk the field
+// from its end so that its beginning, which compression reads first, is the
+// most recently touched data.
 __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ out,
                                                 Geom g)
 {
-    Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
+    __shared__ uint32_t s_red[3][4];
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     const int64_t n4 = vec ? n / 4 : 0;
-    // walk from the end so that the first chunks are the most recently read
     for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) {
         const float4 v = reinterpret_cast<const float4*>(x)[i];
         const float e[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            if (!__builtin_isfinite(e[j])) { bad = 1u; continue; }
             const uint32_t key = float_key(e[j]);
-            lo = min(lo, key);
-            hi = max(hi, key);
+            const bool fin = __builtin_isfinite(e[j]);
+            bad |= fin ? 0u : 1u;
+            lo = fin ? min(lo, key) : lo;
+            hi = fin ? max(hi, key) : hi;
         }
     }
     for (int64_t i = 4 * n4 + tid; i < n; i += stride) {
         const float e = x[i];
-        if (!__builtin_isfinite(e)) { bad = 1u; continue; }
         const uint32_t key = float_key(e);
-        lo = min(lo, key);
-        hi = max(hi, key);
+        const bool fin = __builtin_isfinite(e);
+        bad |= fin ? 0u : 1u;
+        lo = fin ? min(lo, key) : lo;
+        hi = fin ? max(hi, key) : hi;
     }
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {
@@ -546,28 +653,56 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, sh));
         bad |= (uint32_t)__shfl_xor((int)bad, sh);
     }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&scr->min_key, lo);
-        atomicMax(&scr->max_key, hi);
-        if (bad) atomicOr(&scr->nonfinite, 1u);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* part = reinterpret_cast<uint32_t*>(out + g.minmax_off) + 4 * blockIdx.x;
+        part[0] = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
+        part[1] = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+        part[2] = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
     }
 }
 
-__global__ void k_params(uint8_t* __restrict__ out, Geom g, double eb)
+// Fold the partial ranges and derive the eb parameters (one block):
+// eb_abs = eb * (vmax - vmin) in double (a constant field uses eb * |vmax|,
+// or eb if that is 0), ebx2 = fp32(2 eb_abs), inv = fp32(1 / (double)ebx2).
+__global__ __launch_bounds__(256) void k_params(uint8_t* __restrict__ out, Geom g, double eb, int nparts)
 {
+    __shared__ uint32_t s_red[3][4];
     Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
+    const uint32_t* part = reinterpret_cast<const uint32_t*>(out + g.minmax_off);
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        lo = min(lo, part[4 * i]);
+        hi = max(hi, part[4 * i + 1]);
+        bad |= part[4 * i + 2];
+    }
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, sh));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, sh));
+        bad |= (uint32_t)__shfl_xor((int)bad, sh);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    lo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
+    hi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+    bad = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
     uint32_t status = 0;
-    float e2 = 0.0f, iv = 0.0f, lo = 0.0f, hi = 0.0f;
-    if (scr->nonfinite) {
+    float e2 = 0.0f, iv = 0.0f, flo = 0.0f, fhi = 0.0f;
+    if (bad) {
         status = kErrNonfinite;
     } else {
-        lo = key_float(scr->min_key);
-        hi = key_float(scr->max_key);
-        const double range = (double)hi - (double)lo;
+        flo = key_float(lo);
+        fhi = key_float(hi);
+        const double range = (double)fhi - (double)flo;
         double eb_abs;
         if (range > 0.0) eb_abs = eb * range;
         else {
-            const double a = __builtin_fabs((double)hi);
+            const double a = __builtin_fabs((double)fhi);
             eb_abs = eb * (a > 0.0 ? a : 1.0);
         }
         e2 = (float)(2.0 * eb_abs);
@@ -577,8 +712,8 @@ __global__ void k_params(uint8_t* __restrict__ out, Geom g, double eb)
     }
     *reinterpret_cast<float*>(out + kOffEbx2) = e2;
     *reinterpret_cast<float*>(out + kOffInv) = iv;
-    *reinterpret_cast<float*>(out + kOffVmin) = lo;
-    *reinterpret_cast<float*>(out + kOffVmax) = hi;
+    *reinterpret_cast<float*>(out + kOffVmin) = flo;
+    *reinterpret_cast<float*>(out + kOffVmax) = fhi;
     if (status) {
         *reinterpret_cast<uint32_t*>(out + kOffStatus) = status;
         *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off;
@@ -590,7 +725,15 @@ __global__ void k_params(uint8_t* __restrict__ out, Geom g, double eb)
 template <int RANK, bool VEC4>
 static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_compress<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(256), 0, st, x, out, g);
+    // persistent grid: as many workgroups as stay resident, at most one per chunk
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4>, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t resident = (int64_t)cus * per_cu;
+    const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
+    hipLaunchKernelGGL((k_compress<RANK, VEC4>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
     return hipGetLastError();
 }
 
@@ -605,11 +748,11 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
     if (rel) {
         const int64_t n = g.n[0] * g.n[1] * g.n[2];
         int64_t blocks = (n / 4 + 255) / 256;
-        if (blocks > 2048) blocks = 2048;
+        if (blocks > kMinmaxBlocks) blocks = kMinmaxBlocks;
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, out, g, eb);
+        hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, g, eb, (int)blocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);

@@ -9,12 +9,16 @@
 
 namespace fz {
 
-// lane l receives lane l-1's value, lane 0 receives 0 (DPP wave_shr:1).
-// Lane 0 is zeroed explicitly: the compiler may leave the DPP destination of
-// a lane without a source uninitialized.
+// lane l receives lane l-1's value (DPP wave_shr:1).  Lane 0 receives an
+// unspecified value: the compiler may leave the DPP destination of a lane
+// without a source uninitialized, so callers mask it.
+__device__ __forceinline__ int shift_up1_raw(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
 __device__ __forceinline__ int shift_up1(int v, int lane)
 {
-    const int r = __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+    const int r = shift_up1_raw(v);
     return lane == 0 ? 0 : r;
 }
 
@@ -53,18 +57,25 @@ constexpr uint32_t kPrequantLimit = 0x4F000000u << 1;  // bits(2^31) << 1
 
 __device__ __forceinline__ uint32_t absu(int d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
 
+typedef short fz_short2 __attribute__((ext_vector_type(2)));
+
 // Sign-magnitude 16-bit codes of d[i] and d[i+16] packed into one word
-// (Sec. 3.2: sign in the MSB, magnitude below).  `macc` collects the largest
-// magnitude so that one compare per step detects codes that need an escape.
-__device__ __forceinline__ void pack_codes(const int (&d)[32], uint32_t (&P)[16], uint32_t& macc)
+// (Sec. 3.2: sign in the MSB, magnitude below), computed on the packed low
+// halves with 16-bit lane arithmetic.  `eacc` collects d + 32767 as unsigned
+// so that one compare per step (> 65534) finds deltas outside [-32767, 32767],
+// whose codes the escape path then replaces.
+__device__ __forceinline__ void pack_codes(const int (&d)[32], uint32_t (&P)[16], uint32_t& eacc)
 {
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        uint32_t m0 = absu(d[i]), m1 = absu(d[i + 16]);
-        macc = max(macc, max(m0, m1));
-        P[i] = (m0 & 0xFFFFu) | (m1 << 16) | (((uint32_t)d[i] >> 16) & 0x8000u) | ((uint32_t)d[i + 16] & 0x80000000u);
+        const uint32_t x = __builtin_amdgcn_perm((uint32_t)d[i + 16], (uint32_t)d[i], 0x05040100u);
+        const fz_short2 xs = __builtin_bit_cast(fz_short2, x);
+        const fz_short2 mag = __builtin_elementwise_max(xs, (fz_short2)0 - xs);
+        P[i] = __builtin_bit_cast(uint32_t, mag) | (x & 0x80008000u);
+        eacc = max(eacc, max((uint32_t)d[i] + 32767u, (uint32_t)d[i + 16] + 32767u));
     }
 }
+constexpr uint32_t kEscapeLimit = 65534u;
 
 // In-register bit transpose: on entry P[i] holds code i (low half) and code
 // i+16 (high half); on exit P[b] bit m = bit b of code m (Sec. 3.3's
@@ -112,10 +123,13 @@ __device__ __forceinline__ float key_float(uint32_t k)
 
 __device__ __forceinline__ void chunk_box(const Geom& g, int64_t c, int64_t org[3], int64_t ext[3])
 {
+    // chunk counts stay below 2^31, so 32-bit division suffices
+    const uint32_t cc = (uint32_t)c, g2 = (uint32_t)g.grid[2], g1 = (uint32_t)g.grid[1];
+    const uint32_t q2 = cc / g2;
     int64_t ci[3];
-    ci[2] = c % g.grid[2];
-    ci[1] = (c / g.grid[2]) % g.grid[1];
-    ci[0] = c / (g.grid[2] * g.grid[1]);
+    ci[2] = cc - q2 * g2;
+    ci[1] = q2 % g1;
+    ci[0] = q2 / g1;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         org[i] = ci[i] * g.box[i];

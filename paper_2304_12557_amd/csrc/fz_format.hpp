@@ -54,25 +54,26 @@ constexpr uint32_t kErrNonfinite = 1u, kErrEbRange = 2u, kErrOutlierCap = 4u;
 struct Scratch {
     uint32_t ticket;      // chunk tickets, in launch order
     uint32_t pre_status;  // errors found before the main pass (REL params)
-    uint32_t min_key;     // order-preserving keys of the value range
-    uint32_t max_key;
-    uint32_t nonfinite;
-    uint32_t pad[11];
-    // followed by uint64_t state[n_chunks] at byte 64
+    uint32_t pad[14];
+    // followed by a copy of the Geom at byte 64 (read by out-of-line device
+    // code) and by uint64_t state[n_chunks] at byte kScratchStateOff
 };
-constexpr int kScratchStateOff = 64;
+constexpr int kScratchGeomOff = 64;
+constexpr int kScratchStateOff = 512;
+// per-block partial value ranges of the REL pass, after the look-back state
+constexpr int kMinmaxBlocks = 2048;
 
 // lookback state word: flag in the top 2 bits, value (16-B units) below
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kValueMask = (1ull << 62) - 1;
 
-struct Geom {
+struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into the scratch)
     int rank;
     int box[3];
     int64_t n[3];     // slowest-first, trailing unused = 1
     int64_t grid[3];  // chunks per dimension
     int64_t n_chunks;
     int64_t table_off, flags_off, payload_off;  // = header bytes
-    int64_t scratch_off, bound;                 // bound includes the scratch
+    int64_t scratch_off, minmax_off, bound;     // bound includes the scratch
 };
 
 inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
@@ -84,6 +85,9 @@ inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
         if (dims[i] == 0 || dims[i] > (1ull << 40)) return false;
         g->n[i] = (int64_t)dims[i];
     }
+    // the contiguous extent of a 2-D/3-D field stays below 2^25 so that lane
+    // offsets inside one step fit in 32 bits
+    if (rank >= 2 && dims[rank - 1] >= (1ull << 25)) return false;
     if (rank == 3) { g->box[0] = 16; g->box[1] = 32; g->box[2] = 64; }
     if (rank == 2) { g->box[0] = 32; g->box[1] = 1024; }
     if (rank == 1) { g->box[0] = 32768; }
@@ -99,7 +103,8 @@ inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
     g->payload_off = g->flags_off + (int64_t)kFlagBytesPerChunk * g->n_chunks;
     int64_t worst = g->payload_off + g->n_chunks * kChunkPayloadBound;
     g->scratch_off = (worst + 255) / 256 * 256;
-    g->bound = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
+    g->minmax_off = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
+    g->bound = g->minmax_off + 16 * kMinmaxBlocks;
     return true;
 }
 
