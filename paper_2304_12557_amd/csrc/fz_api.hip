@@ -6,7 +6,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "../../include/fz.h"
+#include "fz.h"
 #include "fz_format.hpp"
 #include "fz_kernels.hpp"
 
