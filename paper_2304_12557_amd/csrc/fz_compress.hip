@@ -84,26 +84,32 @@ __device__ __forceinline__ void prequant32(const float (&v)[32], float inv, uint
 }
 
 // ------------------------------------------------------------------ loaders
+// Interior loads go through a buffer resource whose base is the (uniform)
+// first value of the step: a lane keeps one 32-bit byte offset for the whole
+// chunk and the row offsets are uniform, so no 64-bit per-lane address is
+// held in registers.
+typedef uint32_t fz_u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferFlags = 0x00020000;  // dword 3 of a raw buffer resource (gfx9 data format 32)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const float* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, -1, kBufferFlags);
+}
+
 template <int CNT, bool VEC4>
-__device__ __forceinline__ void load_run(const float* __restrict__ p, float* v)
+__device__ __forceinline__ void load_run(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float* v)
 {
     if (VEC4) {
 #pragma unroll
         for (int j = 0; j < CNT / 4; j++) {
-            const float4 t = *reinterpret_cast<const float4*>(p + 4 * j);
-            v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
+            const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16u * j, soff, 0);
+            v[4 * j] = __uint_as_float(t.x); v[4 * j + 1] = __uint_as_float(t.y);
+            v[4 * j + 2] = __uint_as_float(t.z); v[4 * j + 3] = __uint_as_float(t.w);
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < CNT; j++) v[j] = p[j];
+        for (int j = 0; j < CNT; j++) v[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + 4u * j, soff, 0));
     }
-}
-
-template <int CNT>
-__device__ __forceinline__ void load_run_masked(const float* __restrict__ p, float* v, int valid)
-{
-#pragma unroll
-    for (int j = 0; j < CNT; j++) v[j] = j < valid ? p[j] : 0.0f;
 }
 
 // Per-chunk, per-lane geometry.  step_base() is uniform (scalar); lane
@@ -172,8 +178,9 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
                 for (int c = 0; c < 8; c++) v[8 * r + c] = p[min(8 * px + c, ex)];
             }
         } else {
+            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
 #pragma unroll
-            for (int r = 0; r < 4; r++) load_run<8, VEC4>(b + l.off + r * nx, v + 8 * r);
+            for (int r = 0; r < 4; r++) load_run<8, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 8 * r);
         }
     } else if (RANK == 2) {
         const int64_t nx = g.n[1];
@@ -187,8 +194,9 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
                 for (int c = 0; c < 16; c++) v[16 * r + c] = p[min(16 * lane + c, ex)];
             }
         } else {
+            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
 #pragma unroll
-            for (int r = 0; r < 2; r++) load_run<16, VEC4>(b + l.off + r * nx, v + 16 * r);
+            for (int r = 0; r < 2; r++) load_run<16, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 16 * r);
         }
     } else {
         if (EDGE) {
@@ -199,7 +207,7 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
                 v[m] = b[i < last ? i : last];
             }
         } else {
-            load_run<32, VEC4>(b + l.off, v);
+            load_run<32, VEC4>(step_rsrc(b), 4u * l.off, 0u, v);
         }
     }
 }
@@ -241,7 +249,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
 #pragma unroll
         for (int c = 0; c < 16; c++) qprev[c] = qh[16 + c];
     }
-#pragma unroll(ESC ? 1 : 4)
+#pragma unroll ESC ? 1 : 4
     for (int t = 0; t < 4; t++) {
         const int s = 4 * k + t;
         if (EDGE) {
@@ -370,9 +378,11 @@ __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom
 // edge, or a layer whose deltas need escapes (computed again with logging).
 // It loads its own inputs, writes the layer's bricks to Wl and returns
 // (escape count << 32) | max-|p| bits.  The geometry is read from the copy
-// in the scratch so that nothing large crosses the call.
+// in the scratch so that nothing large crosses the call.  It stays a real
+// call: inlined, its registers would push the fast path into spills, while
+// as a call the register saves happen only on this path.
 template <int RANK, bool VEC4>
-__device__ __forceinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
+__device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
                                             int64_t c, int k, float inv, int lane, uint32_t* Wl, uint32_t* oidx,
                                             int32_t* oval)
 {
