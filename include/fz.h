@@ -81,6 +81,7 @@ typedef struct {
 #define FZ_STATUS_BIT_NONFINITE 1u
 #define FZ_STATUS_BIT_EB_RANGE 2u
 #define FZ_STATUS_BIT_OUTLIER_CAP 4u
+#define FZ_STATUS_BIT_INTERNAL 0x80000000u /* a consistency check of the library failed: the stream is invalid */
 
 /* Bytes the caller must provide as d_out of fz_compress: the worst-case
  * stream (every data block nonzero plus the escape cap) followed by the

@@ -1,19 +1,21 @@
-// fz_compress.hip -- single-pass compression kernel of libfzmi (gfx950).
+// fz_compress.hip -- compression kernels of libfzmi (gfx950).
 //
-// Persistent workgroups of 4 waves take chunks by ticket.  In a chunk, wave k
-// handles layer k (4 steps), one lane per 32-code patch.  Per step a lane
-// prequantizes its 32 fp32 values (Sec. 2.3), applies the Lorenzo difference
-// on the integers (Sec. 2.3 / 3.2; the previous step sits in the same lane's
-// registers, the other neighbours come from adjacent lanes), maps the deltas
-// to sign-magnitude 16-bit codes (Sec. 3.2) with packed 16-bit arithmetic,
-// and bit-transposes the 32 codes in registers (the bitshuffle of Sec. 3.3).
-// After its 4 steps a lane holds 16 bricks (one per bit plane); a ballot per
-// plane gives the bit flags of the zero-block encoder (Sec. 3.4).  Wave 0
-// then resolves the chunk's payload offset with a decoupled look-back (the
-// device-wide exclusive prefix sum of Sec. 3.4, without a second kernel)
-// while the other waves already load the next chunk, and every lane stores
-// its nonzero bricks with coalesced 16-byte writes.  No intermediate array
-// touches HBM.
+// k_compress: persistent workgroups of 4 waves take chunks by ticket.  In a
+// chunk, wave k handles layer k (4 steps), one lane per 32-code patch.  Per
+// step a lane prequantizes its 32 fp32 values (Sec. 2.3), applies the Lorenzo
+// difference on the integers (Sec. 2.3 / 3.2; the previous step sits in the
+// same lane's registers, the other neighbours come from adjacent lanes), maps
+// the deltas to sign-magnitude 16-bit codes (Sec. 3.2) with packed 16-bit
+// arithmetic, and bit-transposes the 32 codes in registers (the bitshuffle of
+// Sec. 3.3).  After its 4 steps a lane holds 16 bricks (one per bit plane); a
+// ballot per plane gives the bit flags of the zero-block encoder (Sec. 3.4),
+// which go straight to their place in the stream, and the nonzero bricks are
+// compacted into the chunk's staging slot with coalesced 16-byte writes while
+// the next chunk's loads are in flight.  No chunk waits for another.
+//
+// k_move: the device-wide prefix sum over the chunk sizes and the final
+// compaction (Sec. 3.4): one workgroup per chunk finds its offset from the
+// published sizes and copies its staged payload into the stream.
 #include <hip/hip_runtime.h>
 
 #include "fz_device.hpp"
@@ -423,13 +425,6 @@ __device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x,
     return err;
 }
 
-// Decoupled look-back (single-pass exclusive prefix sum over chunks), run by
-// one whole wave: publish this chunk's aggregate, then read the states of the
-// 64 preceding chunks at once.  If every chunk up to the nearest one with a
-// published inclusive prefix has at least its aggregate, the exclusive prefix
-// is their sum; without an inclusive prefix in the window, the window slides
-// back by 64.  Tickets are taken in order, so every chunk waited on belongs to
-// a running workgroup that publishes its aggregate before it waits itself.
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
 {
 #pragma unroll
@@ -441,34 +436,33 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
     return v;
 }
 
-__device__ __forceinline__ uint64_t lookback(uint64_t* state, int64_t c, uint64_t agg, int lane)
+// Exclusive prefix of chunk c's size over the chunk sizes (the device-wide
+// prefix sum of Sec. 3.4), run by one whole wave after every size has been
+// published: read the 64 preceding states at once and add their sizes back to
+// the nearest chunk that already published its inclusive prefix (sliding the
+// window back by 64 when there is none), then publish c's inclusive prefix.
+// Nothing is waited for; a state without a size (impossible once the
+// compression kernel has finished) makes it return false.
+__device__ __forceinline__ bool chunk_prefix(uint64_t* state, int64_t c, uint64_t units, int lane, uint64_t& excl)
 {
-    if (lane == 0)
-        __hip_atomic_store(&state[c], (c == 0 ? kFlagIncl : kFlagAgg) | agg, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    if (c == 0) return 0;
-    uint64_t excl = 0;
+    excl = 0;
     int64_t top = c - 1;
-    for (;;) {
+    while (top >= 0) {
         const int64_t j = top - lane;
         const uint64_t v = j >= 0 ? __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                   : kFlagIncl;  // before chunk 0: inclusive prefix 0
         const uint64_t f = v & ~kValueMask;
         const uint64_t incl = __ballot(f == kFlagIncl);
-        const uint64_t notready = __ballot(f == 0);
         const int first = incl ? __builtin_ctzll(incl) : 64;
         const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-        if (notready & need) {
-            __builtin_amdgcn_s_sleep(2);
-            continue;
-        }
+        if (__ballot(f == 0) & need) return false;
         excl += wave_sum64(lane <= first ? (v & kValueMask) : 0ull);
         if (first < 64) break;
         top -= 64;
     }
     if (lane == 0)
-        __hip_atomic_store(&state[c], kFlagIncl | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return excl;
+        __hip_atomic_store(&state[c], kFlagIncl | (excl + units), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 template <int RANK, bool VEC4>
@@ -476,7 +470,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
 {
     __shared__ uint32_t s_err;
     __shared__ uint32_t s_nnz[kLayers], s_nout[kLayers];
-    __shared__ uint64_t s_off, s_chunk;
+    __shared__ uint64_t s_chunk;
     __shared__ uint32_t s_oidx[kLayers][kLayerOutlierCap];
     __shared__ int32_t s_oval[kLayers][kLayerOutlierCap];
     __shared__ uint32_t s_w[kLayers][kPlanes * 4 * 64];  // bricks of each wave's layer
@@ -554,48 +548,40 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
             l = lane_geo<RANK>(g, cn, lane);
             if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
         }
+        // the chunk's size goes to its state word (the placement kernel turns
+        // the sizes into offsets); its payload is assembled in its staging slot
         const uint32_t tn = s_nnz[0] + s_nnz[1] + s_nnz[2] + s_nnz[3];
-        if (wave == 0) {
-            const uint32_t to = s_nout[0] + s_nout[1] + s_nout[2] + s_nout[3];
+        const uint32_t to = s_nout[0] + s_nout[1] + s_nout[2] + s_nout[3];
+        uint8_t* slot = out + g.stage_off + kStageSlotBytes * c;
+        if (threadIdx.x == 0) {
             const uint64_t units = tn + (to + 1) / 2;
-            const uint64_t excl = lookback(state, c, units, lane);
-            if (lane == 0) {
-                s_off = excl;
-                uint32_t* tab = reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c);
-                tab[0] = (uint32_t)excl;
-                tab[1] = to;
-                atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
-                atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
-                if (s_err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), s_err);
-                s_err = 0;
-                if (c == g.n_chunks - 1)
-                    *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (excl + units);
-                if (to & 1u) {  // escape pairs are padded to 16 bytes with a zero pair
-                    uint8_t* pairs = out + g.payload_off + 16 * (excl + tn);
-                    *reinterpret_cast<uint2*>(pairs + 8 * to) = make_uint2(0u, 0u);
-                }
-            }
+            state[c] = kFlagAgg | units;
+            reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[1] = to;
+            atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
+            atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
+            if (s_err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), s_err);
+            s_err = 0;
+            if (to & 1u)  // escape pairs are padded to 16 bytes with a zero pair
+                *reinterpret_cast<uint2*>(slot + 16 * tn + 8 * to) = make_uint2(0u, 0u);
         }
-        __syncthreads();
 
         // compaction: nonzero bricks in (layer, plane, patch) order
-        uint64_t base = s_off;
+        uint64_t base = 0;
         for (int w = 0; w < wave; w++) base += s_nnz[w];
-        uint8_t* pay = out + g.payload_off;
 #pragma unroll
         for (int b = 0; b < 16; b++) {
             if (F[b] == 0) continue;  // uniform: a bit plane without nonzero bricks
             if ((F[b] >> lane) & 1ull) {
                 const uint64_t pos = base + mbcnt(F[b]);
                 const uint32_t* w = Wl + b * 4 * 64 + lane;
-                *reinterpret_cast<uint4*>(pay + 16 * pos) = make_uint4(w[0], w[64], w[128], w[192]);
+                *reinterpret_cast<uint4*>(slot + 16 * pos) = make_uint4(w[0], w[64], w[128], w[192]);
             }
             base += __popcll(F[b]);
         }
         if (nout) {
             uint32_t first = 0;
             for (int w = 0; w < wave; w++) first += s_nout[w];
-            uint32_t* pairs = reinterpret_cast<uint32_t*>(pay + 16 * (s_off + tn));
+            uint32_t* pairs = reinterpret_cast<uint32_t*>(slot + 16 * tn);
             for (int i = lane; i < nout; i += 64) {
                 pairs[2 * (first + i)] = s_oidx[wave][i];
                 pairs[2 * (first + i) + 1] = (uint32_t)s_oval[wave][i];
@@ -605,6 +591,37 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         c = cn;
         __syncthreads();  // the LDS counts and logs are reused by the next chunk
     }
+}
+
+// Placement (Sec. 3.4's prefix sum and compaction), one workgroup per
+// chunk: wave 0 turns the chunk's size into its offset, then the workgroup
+// copies the staged payload into the stream and fills the chunk table.
+__global__ __launch_bounds__(256) void k_move(uint8_t* __restrict__ out, Geom g)
+{
+    __shared__ uint64_t s_excl;
+    __shared__ uint32_t s_ok;
+    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
+    if (scr->pre_status) return;  // nothing was compressed (uniform)
+    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
+    const int64_t c = blockIdx.x;
+    const uint64_t units = state[c] & kValueMask;
+    if (threadIdx.x < 64) {
+        uint64_t excl = 0;
+        const bool ok = chunk_prefix(state, c, units, threadIdx.x, excl);
+        if (threadIdx.x == 0) {
+            s_excl = excl;
+            s_ok = ok ? 1u : 0u;
+            if (!ok) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
+            reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[0] = (uint32_t)excl;
+            if (c == g.n_chunks - 1)
+                *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (excl + units);
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const uint4* src = reinterpret_cast<const uint4*>(out + g.stage_off + kStageSlotBytes * c);
+    uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + s_excl;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)units; i += 256) dst[i] = src[i];
 }
 
 // ----------------------------------------------------------- setup kernels
@@ -744,6 +761,9 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
     const int64_t resident = (int64_t)cus * per_cu;
     const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
     hipLaunchKernelGGL((k_compress<RANK, VEC4>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_move, dim3((unsigned)g.n_chunks), dim3(256), 0, st, out, g);
     return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ constexpr int kOffMagic = 0, kOffVersion = 4, kOffHdrBytes = 6, kOffStatus = 8, 
 
 // status bits
 constexpr uint32_t kErrNonfinite = 1u, kErrEbRange = 2u, kErrOutlierCap = 4u;
+constexpr uint32_t kErrInternal = 0x80000000u;  // a consistency check of the library failed
 
 // scratch (after the worst-case stream) used by one compression
 struct Scratch {
@@ -60,10 +61,14 @@ struct Scratch {
 };
 constexpr int kScratchGeomOff = 64;
 constexpr int kScratchStateOff = 512;
-// per-block partial value ranges of the REL pass, after the look-back state
+// per-block partial value ranges of the REL pass, after the chunk states
 constexpr int kMinmaxBlocks = 2048;
+// staging: chunk c's compacted payload is assembled at stage_off + c * bound
+// by the compression kernel and moved to its place in the stream afterwards
+constexpr int64_t kStageSlotBytes = kChunkPayloadBound;
 
-// lookback state word: flag in the top 2 bits, value (16-B units) below
+// chunk state word (payload size in 16-B units, then its inclusive prefix):
+// flag in the top 2 bits, value below
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kValueMask = (1ull << 62) - 1;
 
 struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into the scratch)
@@ -73,7 +78,8 @@ struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into
     int64_t grid[3];  // chunks per dimension
     int64_t n_chunks;
     int64_t table_off, flags_off, payload_off;  // = header bytes
-    int64_t scratch_off, minmax_off, bound;     // bound includes the scratch
+    int64_t scratch_off, minmax_off, stage_off;  // scratch after the worst-case stream
+    int64_t bound;                               // bound includes the scratch and the staging
 };
 
 inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
@@ -104,7 +110,8 @@ inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
     int64_t worst = g->payload_off + g->n_chunks * kChunkPayloadBound;
     g->scratch_off = (worst + 255) / 256 * 256;
     g->minmax_off = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
-    g->bound = g->minmax_off + 16 * kMinmaxBlocks;
+    g->stage_off = (g->minmax_off + 16 * kMinmaxBlocks + 255) / 256 * 256;
+    g->bound = g->stage_off + g->n_chunks * kStageSlotBytes;
     return true;
 }
 
