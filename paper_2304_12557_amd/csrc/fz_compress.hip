@@ -13,9 +13,10 @@
 // compacted into the chunk's staging slot with coalesced 16-byte writes while
 // the next chunk's loads are in flight.  No chunk waits for another.
 //
-// k_move: the device-wide prefix sum over the chunk sizes and the final
-// compaction (Sec. 3.4): one workgroup per chunk finds its offset from the
-// published sizes and copies its staged payload into the stream.
+// k_scan + k_move: the device-wide prefix sum over the chunk sizes and the
+// final compaction (Sec. 3.4): one workgroup scans the published sizes into
+// the chunk table, then one workgroup per chunk copies its staged payload to
+// its offset.
 #include <hip/hip_runtime.h>
 
 #include "fz_device.hpp"
@@ -425,46 +426,6 @@ __device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x,
     return err;
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
-{
-#pragma unroll
-    for (int sh = 32; sh > 0; sh >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, sh);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), sh);
-        v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
-
-// Exclusive prefix of chunk c's size over the chunk sizes (the device-wide
-// prefix sum of Sec. 3.4), run by one whole wave after every size has been
-// published: read the 64 preceding states at once and add their sizes back to
-// the nearest chunk that already published its inclusive prefix (sliding the
-// window back by 64 when there is none), then publish c's inclusive prefix.
-// Nothing is waited for; a state without a size (impossible once the
-// compression kernel has finished) makes it return false.
-__device__ __forceinline__ bool chunk_prefix(uint64_t* state, int64_t c, uint64_t units, int lane, uint64_t& excl)
-{
-    excl = 0;
-    int64_t top = c - 1;
-    while (top >= 0) {
-        const int64_t j = top - lane;
-        const uint64_t v = j >= 0 ? __hip_atomic_load(&state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                  : kFlagIncl;  // before chunk 0: inclusive prefix 0
-        const uint64_t f = v & ~kValueMask;
-        const uint64_t incl = __ballot(f == kFlagIncl);
-        const int first = incl ? __builtin_ctzll(incl) : 64;
-        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-        if (__ballot(f == 0) & need) return false;
-        excl += wave_sum64(lane <= first ? (v & kValueMask) : 0ull);
-        if (first < 64) break;
-        top -= 64;
-    }
-    if (lane == 0)
-        __hip_atomic_store(&state[c], kFlagIncl | (excl + units), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
 template <int RANK, bool VEC4>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
 {
@@ -593,35 +554,75 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     }
 }
 
-// Placement (Sec. 3.4's prefix sum and compaction), one workgroup per
-// chunk: wave 0 turns the chunk's size into its offset, then the workgroup
-// copies the staged payload into the stream and fills the chunk table.
+// Device-wide exclusive prefix sum over the chunk sizes (Sec. 3.4), one
+// workgroup of 1024 threads walking the sizes in tiles of 8192 chunks: the
+// offsets go to the chunk table, the payload size to the header.
+constexpr int kScanThreads = 1024, kScanPerThread = 8;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(uint8_t* __restrict__ out, Geom g)
+{
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
+    if (scr->pre_status) return;  // nothing was compressed
+    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
+    uint32_t* table = reinterpret_cast<uint32_t*>(out + g.table_off);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t carry = 0;
+    bool bad = false;
+    for (int64_t base = 0; base < g.n_chunks; base += kScanThreads * kScanPerThread) {
+        const int64_t i0 = base + (int64_t)tid * kScanPerThread;
+        uint32_t u[kScanPerThread], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanPerThread; j++) {
+            u[j] = 0;
+            if (i0 + j < g.n_chunks) {
+                const uint64_t v = state[i0 + j];
+                bad |= (v & ~kValueMask) == 0;  // a chunk without a size (cannot happen)
+                u[j] = (uint32_t)(v & kValueMask);  // at most 4608 units per chunk
+            }
+            sum += u[j];
+        }
+        const uint32_t incl = (uint32_t)wave_incl_scan((int)sum, lane);  // tile sums stay below 2^26
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, tile = 0;
+#pragma unroll
+        for (int w = 0; w < kScanThreads / 64; w++) {
+            before += w < wave ? s_wave[w] : 0u;
+            tile += s_wave[w];
+        }
+        uint64_t off = carry + before + (incl - sum);
+#pragma unroll
+        for (int j = 0; j < kScanPerThread; j++) {
+            if (i0 + j < g.n_chunks) {
+                bad |= off >= (1ull << 32);  // table offsets are 32-bit (64 GiB of payload)
+                table[2 * (i0 + j)] = (uint32_t)off;
+            }
+            off += u[j];
+        }
+        carry += tile;
+        __syncthreads();  // s_wave is rewritten by the next tile
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0) {
+        *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * carry;
+        if (bad) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
+    }
+}
+
+// Final compaction, one workgroup per chunk: copy the staged payload to the
+// chunk's offset.
 __global__ __launch_bounds__(256) void k_move(uint8_t* __restrict__ out, Geom g)
 {
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_ok;
     const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
-    if (scr->pre_status) return;  // nothing was compressed (uniform)
-    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
+    if (scr->pre_status) return;
     const int64_t c = blockIdx.x;
-    const uint64_t units = state[c] & kValueMask;
-    if (threadIdx.x < 64) {
-        uint64_t excl = 0;
-        const bool ok = chunk_prefix(state, c, units, threadIdx.x, excl);
-        if (threadIdx.x == 0) {
-            s_excl = excl;
-            s_ok = ok ? 1u : 0u;
-            if (!ok) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
-            reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[0] = (uint32_t)excl;
-            if (c == g.n_chunks - 1)
-                *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (excl + units);
-        }
-    }
-    __syncthreads();
-    if (!s_ok) return;
+    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
+    const uint32_t units = (uint32_t)(state[c] & kValueMask);
+    const uint32_t off = reinterpret_cast<const uint32_t*>(out + g.table_off)[2 * c];
     const uint4* src = reinterpret_cast<const uint4*>(out + g.stage_off + kStageSlotBytes * c);
-    uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + s_excl;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)units; i += 256) dst[i] = src[i];
+    uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + off;
+    for (uint32_t i = threadIdx.x; i < units; i += 256) dst[i] = src[i];
 }
 
 // ----------------------------------------------------------- setup kernels
@@ -650,30 +651,21 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int
 {
     __shared__ uint32_t s_red[3][4];
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-    const int64_t n4 = vec ? n / 4 : 0;
-    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) {
-        const float4 v = reinterpret_cast<const float4*>(x)[i];
-        const float e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint32_t key = float_key(e[j]);
-            const bool fin = __builtin_isfinite(e[j]);
-            bad |= fin ? 0u : 1u;
-            lo = fin ? min(lo, key) : lo;
-            hi = fin ? max(hi, key) : hi;
-        }
-    }
-    for (int64_t i = 4 * n4 + tid; i < n; i += stride) {
-        const float e = x[i];
+    auto take = [&](float e) {
         const uint32_t key = float_key(e);
         const bool fin = __builtin_isfinite(e);
         bad |= fin ? 0u : 1u;
         lo = fin ? min(lo, key) : lo;
         hi = fin ? max(hi, key) : hi;
-    }
+    };
+    auto take4 = [&](const float4& v) { take(v.x); take(v.y); take(v.z); take(v.w); };
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    const int64_t n4 = vec ? n / 4 : 0;
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) take4(x4[i]);
+    for (int64_t k = 4 * n4 + tid; k < n; k += stride) take(x[k]);
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, sh));
@@ -763,6 +755,8 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
     hipLaunchKernelGGL((k_compress<RANK, VEC4>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, out, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_move, dim3((unsigned)g.n_chunks), dim3(256), 0, st, out, g);
     return hipGetLastError();
 }
