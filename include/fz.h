@@ -52,7 +52,12 @@ typedef enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 } fz_eb_mode;
 
 /* Field extents, slowest-varying first (a 3-D field 100 x 500 x 500 has
  * n = {100, 500, 500}; x is the contiguous dimension).  rank is 1, 2 or 3;
- * n[rank..2] are ignored. */
+ * n[rank..2] are ignored.  Limits (beyond them every call rejects the dims
+ * with FZ_ERR_ARG, and fz_compress_bound returns 0): every extent in
+ * 1 .. 2^40; for rank 2 and 3 the contiguous extent below 2^25; fewer than
+ * 2^31 chunks (chunk boxes 16x32x64, 32x1024, 32768); the stream's payload
+ * below 64 GiB (offsets are 32-bit in 16-byte units; a larger payload sets
+ * FZ_STATUS_BIT_INTERNAL). */
 typedef struct {
     uint32_t rank;
     uint32_t reserved;
@@ -84,14 +89,18 @@ typedef struct {
 #define FZ_STATUS_BIT_INTERNAL 0x80000000u /* a consistency check of the library failed: the stream is invalid */
 
 /* Bytes the caller must provide as d_out of fz_compress: the worst-case
- * stream (every data block nonzero plus the escape cap) followed by the
- * scratch the single-pass prefix sum uses.  0 on invalid dims. */
+ * stream (every data block nonzero plus the escape cap), then the scratch
+ * (chunk tickets and sizes, partial value ranges) and one staging slot of
+ * the worst-case chunk payload per chunk, where each chunk's compacted
+ * payload waits until the prefix sum has placed it: 1.1 to 1.4 times the
+ * input bytes.  0 on invalid dims. */
 size_t fz_compress_bound(const fz_dims *dims);
 
 /* Bytes of header + chunk table + flags; depends only on the dims. */
 size_t fz_header_bytes(const fz_dims *dims);
 
-/* fz_compress -- Sec. 3.1's pipeline in one pass over the input.
+/* fz_compress -- the compression pipeline of Sec. 3 (one read of the input;
+ * REL mode first reads it once more for the value range).
  *   d_in   : N fp32 values, row-major, slowest-first dims (device, read only)
  *   dims   : host pointer
  *   eb     : absolute error bound (FZ_EB_ABS) or bound relative to the value

@@ -66,3 +66,28 @@ def test_stream_info_parses_oracle_header():
     assert info["status"] == st == 0
     with pytest.raises(fz.FzError):
         fz.stream_info(b"\0" * 128)
+
+
+def test_size_limits():
+    """The library's documented limits: extents up to 2^40, a contiguous
+    extent below 2^25 for rank 2 and 3, fewer than 2^31 chunks."""
+    L = fz.lib()
+
+    def bound(rank, n):
+        d = fz.FzDims()
+        d.rank = rank
+        for i in range(3):
+            d.n[i] = n[i] if i < len(n) else 1
+        return L.fz_compress_bound(ctypes.byref(d)), d
+
+    assert bound(2, (4, (1 << 25) - 1))[0] > 0
+    b, d = bound(2, (4, 1 << 25))
+    assert b == 0
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 1, ctypes.c_void_p(16), None) == 1
+    assert bound(3, (2, 3, 1 << 25))[0] == 0
+    assert bound(1, (1 << 40,))[0] > 0
+    assert bound(1, ((1 << 40) + 1,))[0] == 0
+    # 2^31 chunks: 2^16 x 2^15 chunk boxes of 32 x 1024
+    assert bound(2, (32 << 16, (1 << 15) * 1024 - 1))[0] == 0  # contiguous extent too large first
+    assert bound(3, (16 << 11, 32 << 10, 64 << 10))[0] == 0     # 2^31 chunks
+    assert bound(3, (16 << 11, 32 << 10, (64 << 10) - 64))[0] > 0
