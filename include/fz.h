@@ -126,6 +126,56 @@ int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, 
  * Returns FZ_OK once the work is enqueued. */
 int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
 
+/* ------------------------------------------------------------ batches
+ * Many fields of uneven rank and size in a fixed, small number of launches
+ * (one persistent compression launch over every chunk of every field).  The
+ * bytes each field gets are exactly those of fz_compress / fz_decompress on
+ * that field alone.
+ *
+ * A plan is made once for a list of jobs (it validates them, allocates its
+ * own device tables with hipMalloc and copies them there, synchronously);
+ * fz_batch_run then only enqueues kernels on `stream`: no allocation, no copy
+ * from the host, no synchronization, so a run can be captured in a hipGraph
+ * and replayed.  Buffers named by the jobs must stay valid while runs are
+ * pending; a plan is not thread-safe, and two pending runs of one plan must
+ * be on the same stream. */
+typedef struct {
+    const float *d_in;   /* N fp32 values (device) */
+    fz_dims dims;
+    double eb;
+    int32_t eb_mode;     /* FZ_EB_ABS or FZ_EB_REL */
+    int32_t reserved;
+    void *d_out;         /* fz_compress_bound(&dims) bytes (device) */
+} fz_compress_job;
+
+typedef struct {
+    const void *d_stream;  /* a stream made by fz_compress (device) */
+    fz_dims dims;          /* the dims it was made with */
+    float *d_out;          /* N fp32 values (device) */
+    uint32_t *d_err;       /* optional device u32, as for fz_decompress */
+} fz_decompress_job;
+
+typedef struct fz_batch fz_batch;
+
+/* Make a plan.  On any invalid job returns that job's argument error
+ * (FZ_ERR_ARG, or FZ_ERR_EB_RANGE for an unusable absolute bound) and sets
+ * *out = NULL; FZ_ERR_HIP if the device tables cannot be made. */
+int fz_batch_create_compress(int n, const fz_compress_job *jobs, fz_batch **out);
+int fz_batch_create_decompress(int n, const fz_decompress_job *jobs, fz_batch **out);
+
+/* Enqueue one run of the plan on `stream` (asynchronous). */
+int fz_batch_run(fz_batch *b, void *stream);
+
+/* Autotune the plan's launch shapes (workgroups per CU of the persistent
+ * compression launch, range-pass blocks per field, placement threads per
+ * chunk) by timing each candidate on the plan's own fields; runs the plan
+ * several times and synchronizes `stream`.  Outputs are rewritten with the
+ * same bytes.  Tune before capturing a run in a graph. */
+int fz_batch_tune(fz_batch *b, void *stream);
+
+/* Free the plan's device tables (hipFree synchronizes the device). */
+int fz_batch_destroy(fz_batch *b);
+
 /* Parse a host copy of the first n >= 128 bytes of a stream. */
 int fz_stream_info(const void *h_header, size_t n, fz_info *out);
 

@@ -40,6 +40,16 @@ class FzInfo(ctypes.Structure):
                 ("header_bytes", ctypes.c_uint64)]
 
 
+class FzCompressJob(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("dims", FzDims), ("eb", ctypes.c_double), ("eb_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("d_out", ctypes.c_void_p)]
+
+
+class FzDecompressJob(ctypes.Structure):
+    _fields_ = [("d_stream", ctypes.c_void_p), ("dims", FzDims), ("d_out", ctypes.c_void_p),
+                ("d_err", ctypes.c_void_p)]
+
+
 class FzError(RuntimeError):
     def __init__(self, code, what=""):
         super().__init__("%s: %s (%d)" % (what, ERRORS.get(code, "unknown"), code))
@@ -67,11 +77,23 @@ def lib():
         L.fz_stream_info.restype = ctypes.c_int
         L.fz_strerror.argtypes = [ctypes.c_int]
         L.fz_strerror.restype = ctypes.c_char_p
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.fz_batch_create_compress.argtypes = [ctypes.c_int, ctypes.POINTER(FzCompressJob), pp]
+        L.fz_batch_create_compress.restype = ctypes.c_int
+        L.fz_batch_create_decompress.argtypes = [ctypes.c_int, ctypes.POINTER(FzDecompressJob), pp]
+        L.fz_batch_create_decompress.restype = ctypes.c_int
+        for name in ("fz_batch_run", "fz_batch_tune"):
+            getattr(L, name).argtypes = [vp, vp]
+            getattr(L, name).restype = ctypes.c_int
+        L.fz_batch_destroy.argtypes = [vp]
+        L.fz_batch_destroy.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
 
-SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror"]
+SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror",
+           "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
+           "fz_batch_destroy"]
 
 
 def dims_of(shape):
@@ -161,3 +183,86 @@ def stream_info(header):
 def stream_size(buf):
     """Total stream bytes, read from the header of a compressed buffer."""
     return int(stream_info(buf)["total_bytes"])
+
+
+class Batch:
+    """A plan over many fields (libfzmi's batch layer): ``run()`` enqueues the
+    whole batch in a fixed number of launches, capturable in a graph.
+
+    Compression: ``Batch.compress([(x, eb, mode, out), ...])`` with float32
+    CUDA tensors ``x`` and uint8 CUDA tensors ``out`` of ``compress_bound``
+    bytes (``out=None`` allocates one).  Decompression:
+    ``Batch.decompress([(stream, shape, out, err), ...])``.  The tensors are
+    kept referenced by the plan."""
+
+    def __init__(self, handle, tensors, outs):
+        self._h = ctypes.c_void_p(handle)
+        self._tensors = tensors
+        self.outs = outs
+
+    @classmethod
+    def compress(cls, jobs):
+        import torch
+
+        arr = (FzCompressJob * len(jobs))()
+        keep, outs = [], []
+        for i, (x, eb, mode, out) in enumerate(jobs):
+            if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+                raise ValueError("job %d: x must be a contiguous float32 CUDA tensor" % i)
+            dims = dims_of(x.shape)
+            bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
+            if out is None:
+                out = torch.empty(bound, dtype=torch.uint8, device=x.device)
+            elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
+                raise ValueError("job %d: out must be a uint8 CUDA tensor of at least %d bytes" % (i, bound))
+            arr[i].d_in, arr[i].dims, arr[i].eb = x.data_ptr(), dims, float(eb)
+            arr[i].eb_mode, arr[i].d_out = _mode(mode), out.data_ptr()
+            keep += [x, out]
+            outs.append(out)
+        h = ctypes.c_void_p()
+        rc = lib().fz_batch_create_compress(len(jobs), arr, ctypes.byref(h))
+        if rc:
+            raise FzError(rc, "fz_batch_create_compress")
+        return cls(h.value, keep, outs)
+
+    @classmethod
+    def decompress(cls, jobs):
+        import torch
+
+        arr = (FzDecompressJob * len(jobs))()
+        keep, outs = [], []
+        for i, (s, shape, out, err) in enumerate(jobs):
+            if out is None:
+                out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
+            arr[i].d_stream, arr[i].dims, arr[i].d_out = s.data_ptr(), dims_of(shape), out.data_ptr()
+            arr[i].d_err = err.data_ptr() if err is not None else None
+            keep += [s, out] + ([err] if err is not None else [])
+            outs.append(out)
+        h = ctypes.c_void_p()
+        rc = lib().fz_batch_create_decompress(len(jobs), arr, ctypes.byref(h))
+        if rc:
+            raise FzError(rc, "fz_batch_create_decompress")
+        return cls(h.value, keep, outs)
+
+    def run(self, stream=None):
+        rc = lib().fz_batch_run(self._h, _stream_ptr(stream))
+        if rc:
+            raise FzError(rc, "fz_batch_run")
+        return self.outs
+
+    def tune(self, stream=None):
+        rc = lib().fz_batch_tune(self._h, _stream_ptr(stream))
+        if rc:
+            raise FzError(rc, "fz_batch_tune")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().fz_batch_destroy(self._h)
+        self._h = None
+        self._tensors = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -22,6 +22,10 @@ bool geom_of(const fz_dims* d, Geom* g)
 
 void put_bytes(HeaderImage& h, int off, const void* src, int n) { std::memcpy(reinterpret_cast<uint8_t*>(h.w) + off, src, n); }
 
+}  // namespace
+
+namespace fz {
+
 HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float inv)
 {
     HeaderImage h;
@@ -49,7 +53,16 @@ HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float i
     return h;
 }
 
-}  // namespace
+// eb parameters of an absolute bound: ebx2 = fp32(2 eb), inv = fp32(1 / (double)ebx2);
+// false if they are unusable (2 eb not a normal fp32, or inv not finite)
+bool abs_params(double eb, float* ebx2, float* inv)
+{
+    *ebx2 = (float)(2.0 * eb);
+    *inv = (float)(1.0 / (double)*ebx2);
+    return *ebx2 >= FLT_MIN && std::isfinite(*ebx2) && std::isfinite(*inv) && *inv > 0.0f;
+}
+
+}  // namespace fz
 
 extern "C" {
 
@@ -73,12 +86,7 @@ int fz_compress(const float* d_in, const fz_dims* dims, double eb, int eb_mode, 
     if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
     if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != FZ_EB_ABS && eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
     float ebx2 = 0.0f, inv = 0.0f;
-    if (eb_mode == FZ_EB_ABS) {
-        // eb parameters: ebx2 = fp32(2 eb), inv = fp32(1 / (double)ebx2)
-        ebx2 = (float)(2.0 * eb);
-        inv = (float)(1.0 / (double)ebx2);
-        if (!(ebx2 >= FLT_MIN) || !std::isfinite(ebx2) || !std::isfinite(inv) || !(inv > 0.0f)) return FZ_ERR_EB_RANGE;
-    }
+    if (eb_mode == FZ_EB_ABS && !abs_params(eb, &ebx2, &inv)) return FZ_ERR_EB_RANGE;
     const HeaderImage h = header_image(g, eb, eb_mode, ebx2, inv);
     hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode == FZ_EB_REL, eb,
                                    static_cast<hipStream_t>(stream));

@@ -1,746 +1,87 @@
-// fz_compress.hip -- compression kernels of libfzmi (gfx950).
+// fz_compress.hip -- per-field compression kernels of libfzmi (gfx950).
 //
-// k_compress: persistent workgroups of 4 waves take chunks by ticket.  In a
-// chunk, wave k handles layer k (4 steps), one lane per 32-code patch.  Per
-// step a lane prequantizes its 32 fp32 values (Sec. 2.3), applies the Lorenzo
-// difference on the integers (Sec. 2.3 / 3.2; the previous step sits in the
-// same lane's registers, the other neighbours come from adjacent lanes), maps
-// the deltas to sign-magnitude 16-bit codes (Sec. 3.2) with packed 16-bit
-// arithmetic, and bit-transposes the 32 codes in registers (the bitshuffle of
-// Sec. 3.3).  After its 4 steps a lane holds 16 bricks (one per bit plane); a
-// ballot per plane gives the bit flags of the zero-block encoder (Sec. 3.4),
-// which go straight to their place in the stream, and the nonzero bricks are
-// compacted into the chunk's staging slot with coalesced 16-byte writes while
-// the next chunk's loads are in flight.  No chunk waits for another.
+// k_compress: persistent workgroups of 4 waves take the chunks of one field by
+// ticket; each chunk's layers, flags and staged payload come from the device
+// code in fz_compress_dev.hpp.  The next chunk's first loads are issued
+// before the current chunk is placed, and no chunk waits for another.
 //
 // k_scan + k_move: the device-wide prefix sum over the chunk sizes and the
 // final compaction (Sec. 3.4): one workgroup scans the published sizes into
 // the chunk table, then one workgroup per chunk copies its staged payload to
-// its offset.
+// its offset.  REL mode runs k_minmax + k_params first (the value range).
 #include <hip/hip_runtime.h>
 
-#include "fz_device.hpp"
+#include "fz_compress_dev.hpp"
 #include "fz_kernels.hpp"
 
 namespace fz {
 
-struct EscapeLog {
-    uint32_t* idx;  // LDS, kLayerOutlierCap entries for this wave
-    int32_t* val;
-    int count;      // escapes seen so far in this layer (may exceed the cap)
-};
-
-// Slow path of a step with at least one escape: codes whose delta does not
-// fit in 15 bits become 0x8000 and their (code index, delta) pair is logged
-// in code-index order (lane-major, then cell).
-__device__ __forceinline__ void log_escapes(const int (&d)[32], uint32_t (&P)[16], EscapeLog& log, uint32_t n0, int lane)
-{
-    uint32_t emask = 0;
-#pragma unroll
-    for (int i = 0; i < 32; i++) emask |= ((uint32_t)d[i] + 32767u > kEscapeLimit ? 1u : 0u) << i;
-    const int cnt = __popc(emask);
-    const int incl = wave_incl_scan(cnt, lane);
-    const int total = __shfl(incl, 63);
-    int pos = log.count + incl - cnt;
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if ((emask >> i) & 1u) {
-            if (pos < kLayerOutlierCap) {
-                log.idx[pos] = n0 + (uint32_t)lane * kPatchCodes + i;
-                log.val[pos] = d[i];
-            }
-            pos++;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-        if ((emask >> i) & 1u) P[i] = (P[i] & 0xFFFF0000u) | kEscape;
-        if ((emask >> (i + 16)) & 1u) P[i] = (P[i] & 0x0000FFFFu) | (kEscape << 16);
-    }
-    log.count += total;
-}
-
-// codes -> escapes -> bit planes, shared tail of every rank's step.  The fast
-// pass (ESC = false) only reports that a step needs escapes; the layer is then
-// redone by the logging pass (ESC = true), which rewrites those codes.
-template <bool ESC>
-__device__ __forceinline__ bool finish_step(const int (&d)[32], uint32_t (&P)[16], EscapeLog& log, uint32_t n0, int lane)
-{
-    uint32_t eacc = 0;
-    pack_codes(d, P, eacc);
-    const bool esc = __ballot(eacc > kEscapeLimit) != 0;
-    if (ESC && esc) log_escapes(d, P, log, n0, lane);
-    transpose16(P);
-    return esc;
-}
-
-// prequantize 32 values; `facc` tracks max |p| (as shifted bits)
-__device__ __forceinline__ void prequant32(const float (&v)[32], float inv, uint32_t& facc, int (&q)[32])
-{
-#pragma unroll
-    for (int i = 0; i < 32; i += 2) {
-        const float p0 = v[i] * inv, p1 = v[i + 1] * inv;
-        facc = max(facc, max(__float_as_uint(p0) << 1, __float_as_uint(p1) << 1));
-        q[i] = (int)__builtin_rintf(p0);
-        q[i + 1] = (int)__builtin_rintf(p1);
-    }
-}
-
-// ------------------------------------------------------------------ loaders
-// Interior loads go through a buffer resource whose base is the (uniform)
-// first value of the step: a lane keeps one 32-bit byte offset for the whole
-// chunk and the row offsets are uniform, so no 64-bit per-lane address is
-// held in registers.
-typedef uint32_t fz_u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kBufferFlags = 0x00020000;  // dword 3 of a raw buffer resource (gfx9 data format 32)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const float* base)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, -1, kBufferFlags);
-}
-
-template <int CNT, bool VEC4>
-__device__ __forceinline__ void load_run(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float* v)
-{
-    if (VEC4) {
-#pragma unroll
-        for (int j = 0; j < CNT / 4; j++) {
-            const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16u * j, soff, 0);
-            v[4 * j] = __uint_as_float(t.x); v[4 * j + 1] = __uint_as_float(t.y);
-            v[4 * j + 2] = __uint_as_float(t.z); v[4 * j + 3] = __uint_as_float(t.w);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < CNT; j++) v[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + 4u * j, soff, 0));
-    }
-}
-
-// Per-chunk, per-lane geometry.  step_base() is uniform (scalar); lane
-// offsets inside a step are 32-bit.
-struct Lane {
-    int64_t org[3], ext[3];
-    int L;
-    bool edge;
-    uint32_t off;  // lane offset of its first value inside a step
-    int ev, eh;    // 3-D: valid rows / columns of the patch; 2-D: columns
-};
-
-template <int RANK>
-__device__ __forceinline__ Lane lane_geo(const Geom& g, int64_t c, int lane)
-{
-    Lane l;
-    chunk_box(g, c, l.org, l.ext);
-    l.L = layers_of(RANK, l.ext[0]);
-    l.edge = false;
-#pragma unroll
-    for (int i = 0; i < 3; i++) l.edge |= l.ext[i] < g.box[i];
-    if (RANK == 3) {
-        const int py = lane & 7, px = lane >> 3;
-        l.off = (uint32_t)(4 * py * g.n[2] + 8 * px);
-        l.ev = clampi(l.ext[1] - 4 * py, 0, 4);
-        l.eh = clampi(l.ext[2] - 8 * px, 0, 8);
-    } else if (RANK == 2) {
-        l.off = (uint32_t)(16 * lane);
-        l.ev = 2;
-        l.eh = clampi(l.ext[1] - 16 * lane, 0, 16);
-    } else {
-        l.off = (uint32_t)(kPatchCodes * lane);
-        l.ev = 1;
-        l.eh = 32;
-    }
-    return l;
-}
-
-// first value of step s (3-D: plane s; 2-D: row 2s; 1-D: value 2048 s) of the chunk
-template <int RANK>
-__device__ __forceinline__ const float* step_base(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s)
-{
-    if (RANK == 3) return x + ((l.org[0] + s) * g.n[1] + l.org[1]) * g.n[2] + l.org[2];
-    if (RANK == 2) return x + (l.org[0] + 2 * s) * g.n[1] + l.org[1];
-    return x + l.org[0] + (int64_t)kStepCodes * s;
-}
-
-// load the lane's 32 values of step s (s = 4k-1 is the halo of layer k).
-// In a chunk cut by the field's edge every index is clamped into the field:
-// cells outside it then hold some in-field value, and their deltas are zeroed
-// later (a delta inside the field never looks at a cell outside it).
-template <int RANK, bool EDGE, bool VEC4>
-__device__ __forceinline__ void load_step(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s, int lane,
-                                          float (&v)[32])
-{
-    const float* b = step_base<RANK>(x, g, l, s);
-    if (RANK == 3) {
-        const int64_t nx = g.n[2];
-        if (EDGE) {
-            const int py = lane & 7, px = lane >> 3;
-            const int ey = (int)l.ext[1] - 1, ex = (int)l.ext[2] - 1;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const float* p = b + (uint32_t)min(4 * py + r, ey) * (uint32_t)nx;
-#pragma unroll
-                for (int c = 0; c < 8; c++) v[8 * r + c] = p[min(8 * px + c, ex)];
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
-#pragma unroll
-            for (int r = 0; r < 4; r++) load_run<8, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 8 * r);
-        }
-    } else if (RANK == 2) {
-        const int64_t nx = g.n[1];
-        if (EDGE) {
-            const int ex = (int)l.ext[1] - 1;
-            const int64_t last = l.ext[0] - 1 - 2 * s;  // last field row relative to the step
-#pragma unroll
-            for (int r = 0; r < 2; r++) {
-                const float* p = b + (r < last ? r : last) * nx;
-#pragma unroll
-                for (int c = 0; c < 16; c++) v[16 * r + c] = p[min(16 * lane + c, ex)];
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
-#pragma unroll
-            for (int r = 0; r < 2; r++) load_run<16, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 16 * r);
-        }
-    } else {
-        if (EDGE) {
-            const int64_t last = l.ext[0] - 1 - (int64_t)kStepCodes * s;
-#pragma unroll
-            for (int m = 0; m < 32; m++) {
-                const int64_t i = (int64_t)l.off + m;
-                v[m] = b[i < last ? i : last];
-            }
-        } else {
-            load_run<32, VEC4>(step_rsrc(b), 4u * l.off, 0u, v);
-        }
-    }
-}
-
-// ------------------------------------------------------------- one layer
-// `h` holds the halo (3-D: the plane before the layer; 2-D: the two rows
-// before it, of which the second is used; 1-D: unused) and `v` the first
-// step, both loaded ahead of time.  The plane-b word of step t goes to
-// Wl[(b * 4 + t) * 64 + lane] in LDS (brick (k, b, lane) = its 4 words) and
-// nz[b] collects their OR for the flags.
-// Returns whether some delta of the layer needs an escape (only the ESC pass
-// logs them).
-template <int RANK, bool EDGE, bool VEC4, bool ESC>
-__device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
-                                      int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
-                                      uint32_t& facc, EscapeLog& log)
-{
-    // the logging pass (ESC) keeps one copy of the step code: it runs rarely
-    // and must not add to the register budget of the fast pass
-    bool esc = false;
-#pragma unroll
-    for (int b = 0; b < 16; b++) nz[b] = 0u;
-    const int py = lane & 7, px = lane >> 3;
-    // previous-step state: 3-D plane (32), 2-D row (16), 1-D last value (uniform)
-    int qprev[32];
-    int carry1 = 0;
-    if (k == 0 || RANK == 1) {
-#pragma unroll
-        for (int i = 0; i < 32; i++) qprev[i] = 0;
-        if (RANK == 1 && k > 0) {
-            uint32_t dummy = 0;
-            carry1 = prequant(x[l.org[0] + (int64_t)kStepCodes * 4 * k - 1], inv, dummy);
-        }
-    } else if (RANK == 3) {
-        prequant32(h, inv, facc, qprev);
-    } else {
-        int qh[32];
-        prequant32(h, inv, facc, qh);
-#pragma unroll
-        for (int c = 0; c < 16; c++) qprev[c] = qh[16 + c];
-    }
-#pragma unroll ESC ? 1 : 4
-    for (int t = 0; t < 4; t++) {
-        const int s = 4 * k + t;
-        if (EDGE) {
-            const int64_t lo = RANK == 3 ? s : RANK == 2 ? 2 * s : (int64_t)kStepCodes * s;
-            if (lo >= l.ext[0]) {
-#pragma unroll
-                for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] = 0u;
-                continue;
-            }
-        }
-        float vn[32];
-        if (t < 3) {
-            bool next = true;
-            if (EDGE) {
-                const int64_t lo = RANK == 3 ? s + 1 : RANK == 2 ? 2 * (s + 1) : (int64_t)kStepCodes * (s + 1);
-                next = lo < l.ext[0];
-            }
-            if (next) load_step<RANK, EDGE, VEC4>(x, g, l, s + 1, lane, vn);
-        }
-        int q[32];
-        prequant32(v, inv, facc, q);
-        int d[32];
-        if (RANK == 3) {
-            int a[32];
-#pragma unroll
-            for (int i = 0; i < 32; i++) {
-                a[i] = q[i] - qprev[i];  // Dz
-                qprev[i] = q[i];
-            }
-            int b[32];
-#pragma unroll
-            for (int c = 0; c < 8; c++) {  // Dy; row 0 takes row 3 of lane-1 (0 for py == 0)
-                const int up = shift_up1_raw(a[24 + c]);
-                b[c] = a[c] - (py == 0 ? 0 : up);
-            }
-#pragma unroll
-            for (int r = 1; r < 4; r++)
-#pragma unroll
-                for (int c = 0; c < 8; c++) b[8 * r + c] = a[8 * r + c] - a[8 * (r - 1) + c];
-#pragma unroll
-            for (int r = 0; r < 4; r++) {  // Dx; column 0 takes column 7 of lane-8 (0 for px == 0)
-                const int left = lane_value(b[8 * r + 7], lane - 8);
-                d[8 * r] = b[8 * r] - (px == 0 ? 0 : left);
-#pragma unroll
-                for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
-            }
-            if (EDGE) {
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-#pragma unroll
-                    for (int c = 0; c < 8; c++)
-                        if (!(r < l.ev && c < l.eh)) d[8 * r + c] = 0;
-            }
-        } else if (RANK == 2) {
-            int b[32];
-#pragma unroll
-            for (int c = 0; c < 16; c++) {  // Dy against the previous row of the same lane
-                b[c] = q[c] - qprev[c];
-                b[16 + c] = q[16 + c] - q[c];
-                qprev[c] = q[16 + c];
-            }
-#pragma unroll
-            for (int r = 0; r < 2; r++) {  // Dx; column 0 takes column 15 of lane-1 (0 at lane 0)
-                const int left = shift_up1_raw(b[16 * r + 15]);
-                d[16 * r] = b[16 * r] - (lane == 0 ? 0 : left);
-#pragma unroll
-                for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
-            }
-            if (EDGE) {
-                const bool r1 = 2 * s + 1 < l.ext[0];
-#pragma unroll
-                for (int c = 0; c < 16; c++) {
-                    if (!(c < l.eh)) d[c] = 0;
-                    if (!(c < l.eh && r1)) d[16 + c] = 0;
-                }
-            }
-        } else {
-            const int left = shift_up1_raw(q[31]);
-            d[0] = q[0] - (lane == 0 ? carry1 : left);
-#pragma unroll
-            for (int m = 1; m < 32; m++) d[m] = q[m] - q[m - 1];
-            carry1 = __builtin_amdgcn_readlane(q[31], 63);
-            if (EDGE) {
-                const int valid = clampi(l.ext[0] - ((int64_t)kStepCodes * s + l.off), 0, 32);
-#pragma unroll
-                for (int m = 0; m < 32; m++)
-                    if (!(m < valid)) d[m] = 0;
-            }
-        }
-        uint32_t P[16];
-        esc |= finish_step<ESC>(d, P, log, (uint32_t)s * kStepCodes, lane);
-#pragma unroll
-        for (int bb = 0; bb < 16; bb++) {
-            Wl[(bb * 4 + t) * 64 + lane] = P[bb];
-            nz[bb] |= P[bb];
-        }
-        if (t < 3) {
-#pragma unroll
-            for (int i = 0; i < 32; i++) v[i] = vn[i];
-        }
-    }
-    return esc;
-}
-
-// Load the halo and the first step of layer k of a chunk ahead of time.
-template <int RANK, bool VEC4>
-__device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom& g, const Lane& l, int k, int lane,
-                                         float (&h)[32], float (&v)[32])
-{
-#pragma unroll
-    for (int i = 0; i < 32; i++) {  // every path defines both, so no old value stays live
-        h[i] = 0.0f;
-        v[i] = 0.0f;
-    }
-    if (k >= l.L) return;
-    if (l.edge) {
-        if (k > 0 && RANK != 1) load_step<RANK, true, VEC4>(x, g, l, 4 * k - 1, lane, h);
-        load_step<RANK, true, VEC4>(x, g, l, 4 * k, lane, v);
-    } else {
-        if (k > 0 && RANK != 1) load_step<RANK, false, VEC4>(x, g, l, 4 * k - 1, lane, h);
-        load_step<RANK, false, VEC4>(x, g, l, 4 * k, lane, v);
-    }
-}
-
-// Out-of-line layer pass for the uncommon cases: a chunk cut by the field's
-// edge, or a layer whose deltas need escapes (computed again with logging).
-// It loads its own inputs, writes the layer's bricks to Wl and returns
-// (escape count << 32) | max-|p| bits.  The geometry is read from the copy
-// in the scratch so that nothing large crosses the call.  It stays a real
-// call: inlined, its registers would push the fast path into spills, while
-// as a call the register saves happen only on this path.
-template <int RANK, bool VEC4>
-__device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
-                                            int64_t c, int k, float inv, int lane, uint32_t* Wl, uint32_t* oidx,
-                                            int32_t* oval)
-{
-    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
-    const Lane l = lane_geo<RANK>(g, c, lane);
-    float h[32], v[32];
-    prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
-    uint32_t nz[16], facc = 0;
-    EscapeLog log{oidx, oval, 0};
-    if (l.edge) layer<RANK, true, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    else layer<RANK, false, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    return ((uint64_t)(uint32_t)log.count << 32) | facc;
-}
-
-// Rare path: a step saw NaN/Inf or |x*inv| >= 2^31.  Re-read the layer's
-// cells and classify them the way the format defines the status bits
-// (halo values belong to the previous layer, which reports them).
-__device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
-                                                 int64_t c, int k, float inv, int lane)
-{
-    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
-    int64_t o[3], e[3];
-    chunk_box(g, c, o, e);
-    uint32_t err = 0;
-    for (int t = 0; t < 4; t++) {
-        const int s = 4 * k + t;
-        for (int m = 0; m < 32; m++) {
-            int64_t r0 = 0, r1 = 0, r2 = 0;
-            if (g.rank == 3) { r0 = s; r1 = 4 * (lane % 8) + m / 8; r2 = 8 * (lane / 8) + m % 8; }
-            else if (g.rank == 2) { r0 = 2 * s + m / 16; r1 = 16 * lane + m % 16; }
-            else { r0 = (int64_t)kStepCodes * s + kPatchCodes * lane + m; }
-            if (r0 >= e[0] || r1 >= e[1] || r2 >= e[2]) continue;
-            const float v = x[((o[0] + r0) * g.n[1] + o[1] + r1) * g.n[2] + o[2] + r2];
-            if (!__builtin_isfinite(v)) err |= kErrNonfinite;
-            else if (!(__builtin_fabsf(v * inv) < 2147483648.0f)) err |= kErrEbRange;
-        }
-    }
-    return err;
-}
-
 template <int RANK, bool VEC4>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
 {
-    __shared__ uint32_t s_err;
-    __shared__ uint32_t s_nnz[kLayers], s_nout[kLayers];
-    __shared__ uint64_t s_chunk;
-    __shared__ uint32_t s_oidx[kLayers][kLayerOutlierCap];
-    __shared__ int32_t s_oval[kLayers][kLayerOutlierCap];
-    __shared__ uint32_t s_w[kLayers][kPlanes * 4 * 64];  // bricks of each wave's layer
-
+    __shared__ CompressLds S;
     Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
-    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keep it scalar
     if (scr->pre_status) return;  // set before this launch: uniform across the grid
     const float inv = *reinterpret_cast<const float*>(out + kOffInv);
 
     if (threadIdx.x == 0) {
-        s_chunk = atomicAdd(&scr->ticket, 1u);
-        s_err = 0;
+        S.ticket = atomicAdd(&scr->ticket, 1u);
+        S.err = 0;
     }
     __syncthreads();
-    int64_t c = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_chunk);
+    int64_t c = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
     if (c >= g.n_chunks) return;
     float h[32], v[32];
     Lane l = lane_geo<RANK>(g, c, lane);
     if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
 
     for (;;) {
-        uint32_t nz[16];
-        uint32_t facc = 0;
-        uint32_t* Wl = s_w[wave];
-        EscapeLog log{s_oidx[wave], s_oval[wave], 0};
-        if (wave < l.L) {
-            bool slow = l.edge;
-            if (!slow) slow = layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
-            if (slow) {  // edge chunk, or escapes to log
-                const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx,
-                                                          log.val);
-                log.count = (int)(r >> 32);
-                facc = max(facc, (uint32_t)r);
-#pragma unroll
-                for (int b = 0; b < 16; b++)
-                    nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
-                            Wl[(b * 4 + 3) * 64 + lane];
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < 16; b++) nz[b] = 0u;
-        }
-        uint32_t err = 0;
-        if (__ballot(facc >= kPrequantLimit)) {
-            err = classify_errors(x, out, g.scratch_off, c, wave, inv, lane);
-#pragma unroll
-            for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
-        }
-        if (log.count > kLayerOutlierCap) err |= kErrOutlierCap;
-        const int nout = log.count < kLayerOutlierCap ? log.count : kLayerOutlierCap;
-
-        // flags of the zero-block encoder: one ballot per bit plane
         uint64_t F[16];
-        uint32_t nnz = 0;
-        uint64_t myflag = 0;
-#pragma unroll
-        for (int b = 0; b < 16; b++) {
-            F[b] = __ballot(nz[b] != 0u);
-            nnz += __popcll(F[b]);
-            myflag = lane == b ? F[b] : myflag;
-        }
-        if (lane < 16)
-            reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
-        if (lane == 0) {
-            s_nnz[wave] = nnz;
-            s_nout[wave] = (uint32_t)nout;
-            if (err) atomicOr(&s_err, err);
-        }
-        if (threadIdx.x == 0) s_chunk = atomicAdd(&scr->ticket, 1u);  // next chunk
+        const int nout = chunk_layer<RANK, VEC4>(x, out, g, c, l, wave, lane, inv, h, v, S, F);
+        if (threadIdx.x == 0) S.ticket = atomicAdd(&scr->ticket, 1u);  // next chunk
         __syncthreads();
-        const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_chunk);
+        const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
         if (cn < g.n_chunks) {  // start loading the next chunk while this one is placed
             l = lane_geo<RANK>(g, cn, lane);
             if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
         }
-        // the chunk's size goes to its state word (the placement kernel turns
-        // the sizes into offsets); its payload is assembled in its staging slot
-        const uint32_t tn = s_nnz[0] + s_nnz[1] + s_nnz[2] + s_nnz[3];
-        const uint32_t to = s_nout[0] + s_nout[1] + s_nout[2] + s_nout[3];
-        uint8_t* slot = out + g.stage_off + kStageSlotBytes * c;
-        if (threadIdx.x == 0) {
-            const uint64_t units = tn + (to + 1) / 2;
-            state[c] = kFlagAgg | units;
-            reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[1] = to;
-            atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
-            atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
-            if (s_err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), s_err);
-            s_err = 0;
-            if (to & 1u)  // escape pairs are padded to 16 bytes with a zero pair
-                *reinterpret_cast<uint2*>(slot + 16 * tn + 8 * to) = make_uint2(0u, 0u);
-        }
-
-        // compaction: nonzero bricks in (layer, plane, patch) order
-        uint64_t base = 0;
-        for (int w = 0; w < wave; w++) base += s_nnz[w];
-#pragma unroll
-        for (int b = 0; b < 16; b++) {
-            if (F[b] == 0) continue;  // uniform: a bit plane without nonzero bricks
-            if ((F[b] >> lane) & 1ull) {
-                const uint64_t pos = base + mbcnt(F[b]);
-                const uint32_t* w = Wl + b * 4 * 64 + lane;
-                *reinterpret_cast<uint4*>(slot + 16 * pos) = make_uint4(w[0], w[64], w[128], w[192]);
-            }
-            base += __popcll(F[b]);
-        }
-        if (nout) {
-            uint32_t first = 0;
-            for (int w = 0; w < wave; w++) first += s_nout[w];
-            uint32_t* pairs = reinterpret_cast<uint32_t*>(slot + 16 * tn);
-            for (int i = lane; i < nout; i += 64) {
-                pairs[2 * (first + i)] = s_oidx[wave][i];
-                pairs[2 * (first + i) + 1] = (uint32_t)s_oval[wave][i];
-            }
-        }
+        chunk_place(out, g, c, wave, lane, F, nout, S);
         if (cn >= g.n_chunks) break;
         c = cn;
         __syncthreads();  // the LDS counts and logs are reused by the next chunk
     }
 }
 
-// Device-wide exclusive prefix sum over the chunk sizes (Sec. 3.4), one
-// workgroup of 1024 threads walking the sizes in tiles of 8192 chunks: the
-// offsets go to the chunk table, the payload size to the header.
-constexpr int kScanThreads = 1024, kScanPerThread = 8;
+__global__ __launch_bounds__(kScanThreads) void k_scan(uint8_t* __restrict__ out, Geom g) { scan_field(out, g); }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan(uint8_t* __restrict__ out, Geom g)
+__global__ __launch_bounds__(256) void k_move(uint8_t* __restrict__ out, Geom g) { move_chunk(out, g, blockIdx.x, 256); }
+
+__global__ __launch_bounds__(256) void k_init(uint8_t* __restrict__ out, Geom g, HeaderImage h)
 {
-    __shared__ uint32_t s_wave[kScanThreads / 64];
-    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
-    if (scr->pre_status) return;  // nothing was compressed
-    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    uint32_t* table = reinterpret_cast<uint32_t*>(out + g.table_off);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint64_t carry = 0;
-    bool bad = false;
-    for (int64_t base = 0; base < g.n_chunks; base += kScanThreads * kScanPerThread) {
-        const int64_t i0 = base + (int64_t)tid * kScanPerThread;
-        uint32_t u[kScanPerThread], sum = 0;
-#pragma unroll
-        for (int j = 0; j < kScanPerThread; j++) {
-            u[j] = 0;
-            if (i0 + j < g.n_chunks) {
-                const uint64_t v = state[i0 + j];
-                bad |= (v & ~kValueMask) == 0;  // a chunk without a size (cannot happen)
-                u[j] = (uint32_t)(v & kValueMask);  // at most 4608 units per chunk
-            }
-            sum += u[j];
-        }
-        const uint32_t incl = (uint32_t)wave_incl_scan((int)sum, lane);  // tile sums stay below 2^26
-        if (lane == 63) s_wave[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, tile = 0;
-#pragma unroll
-        for (int w = 0; w < kScanThreads / 64; w++) {
-            before += w < wave ? s_wave[w] : 0u;
-            tile += s_wave[w];
-        }
-        uint64_t off = carry + before + (incl - sum);
-#pragma unroll
-        for (int j = 0; j < kScanPerThread; j++) {
-            if (i0 + j < g.n_chunks) {
-                bad |= off >= (1ull << 32);  // table offsets are 32-bit (64 GiB of payload)
-                table[2 * (i0 + j)] = (uint32_t)off;
-            }
-            off += u[j];
-        }
-        carry += tile;
-        __syncthreads();  // s_wave is rewritten by the next tile
-    }
-    bad = __syncthreads_or(bad);
-    if (tid == 0) {
-        *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * carry;
-        if (bad) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
-    }
+    init_field(out, g, h, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
-// Final compaction, one workgroup per chunk: copy the staged payload to the
-// chunk's offset.
-__global__ __launch_bounds__(256) void k_move(uint8_t* __restrict__ out, Geom g)
-{
-    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
-    if (scr->pre_status) return;
-    const int64_t c = blockIdx.x;
-    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    const uint32_t units = (uint32_t)(state[c] & kValueMask);
-    const uint32_t off = reinterpret_cast<const uint32_t*>(out + g.table_off)[2 * c];
-    const uint4* src = reinterpret_cast<const uint4*>(out + g.stage_off + kStageSlotBytes * c);
-    uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + off;
-    for (uint32_t i = threadIdx.x; i < units; i += 256) dst[i] = src[i];
-}
-
-// ----------------------------------------------------------- setup kernels
-__global__ void k_init(uint8_t* __restrict__ out, Geom g, HeaderImage h)
-{
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < kHeaderBytes / 4) reinterpret_cast<uint32_t*>(out)[tid] = h.w[tid];
-    if (tid == 0 && (g.n_chunks & 1))  // the chunk table is padded to 16 bytes with zeros
-        *reinterpret_cast<uint2*>(out + g.table_off + 8 * g.n_chunks) = make_uint2(0u, 0u);
-    uint32_t* scr = reinterpret_cast<uint32_t*>(out + g.scratch_off);
-    if (tid < kScratchGeomOff / 4) scr[tid] = 0u;
-    static_assert(sizeof(Geom) % 4 == 0 && kScratchGeomOff + sizeof(Geom) <= kScratchStateOff, "scratch layout");
-    if (tid < (int64_t)(sizeof(Geom) / 4))
-        scr[kScratchGeomOff / 4 + tid] = reinterpret_cast<const uint32_t*>(&g)[tid];
-    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    for (int64_t i = tid; i < g.n_chunks; i += (int64_t)gridDim.x * blockDim.x) state[i] = 0;
-}
-
-// Value range for the relative error bound, two passes without contended
-// atomics: every block writes its partial (min key, max key, non-finite) to
-// the scratch, then k_params folds the partials.  The blocks walk the field
-// from its end so that its beginning, which compression reads first, is the
-// most recently touched data.
 __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ out,
                                                 Geom g)
 {
-    __shared__ uint32_t s_red[3][4];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
-    auto take = [&](float e) {
-        const uint32_t key = float_key(e);
-        const bool fin = __builtin_isfinite(e);
-        bad |= fin ? 0u : 1u;
-        lo = fin ? min(lo, key) : lo;
-        hi = fin ? max(hi, key) : hi;
-    };
-    auto take4 = [&](const float4& v) { take(v.x); take(v.y); take(v.z); take(v.w); };
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-    const int64_t n4 = vec ? n / 4 : 0;
-    const float4* x4 = reinterpret_cast<const float4*>(x);
-    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) take4(x4[i]);
-    for (int64_t k = 4 * n4 + tid; k < n; k += stride) take(x[k]);
-#pragma unroll
-    for (int sh = 32; sh > 0; sh >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, sh));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, sh));
-        bad |= (uint32_t)__shfl_xor((int)bad, sh);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t* part = reinterpret_cast<uint32_t*>(out + g.minmax_off) + 4 * blockIdx.x;
-        part[0] = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
-        part[1] = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
-        part[2] = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
-    }
+    minmax_block(x, n, out, g, blockIdx.x, gridDim.x);
 }
 
-// Fold the partial ranges and derive the eb parameters (one block):
-// eb_abs = eb * (vmax - vmin) in double (a constant field uses eb * |vmax|,
-// or eb if that is 0), ebx2 = fp32(2 eb_abs), inv = fp32(1 / (double)ebx2).
 __global__ __launch_bounds__(256) void k_params(uint8_t* __restrict__ out, Geom g, double eb, int nparts)
 {
-    __shared__ uint32_t s_red[3][4];
-    Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
-    const uint32_t* part = reinterpret_cast<const uint32_t*>(out + g.minmax_off);
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        lo = min(lo, part[4 * i]);
-        hi = max(hi, part[4 * i + 1]);
-        bad |= part[4 * i + 2];
-    }
-#pragma unroll
-    for (int sh = 32; sh > 0; sh >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, sh));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, sh));
-        bad |= (uint32_t)__shfl_xor((int)bad, sh);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    lo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
-    hi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
-    bad = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
-    uint32_t status = 0;
-    float e2 = 0.0f, iv = 0.0f, flo = 0.0f, fhi = 0.0f;
-    if (bad) {
-        status = kErrNonfinite;
-    } else {
-        flo = key_float(lo);
-        fhi = key_float(hi);
-        const double range = (double)fhi - (double)flo;
-        double eb_abs;
-        if (range > 0.0) eb_abs = eb * range;
-        else {
-            const double a = __builtin_fabs((double)fhi);
-            eb_abs = eb * (a > 0.0 ? a : 1.0);
-        }
-        e2 = (float)(2.0 * eb_abs);
-        iv = (float)(1.0 / (double)e2);
-        if (!(e2 >= 1.17549435e-38f) || !__builtin_isfinite(e2) || !__builtin_isfinite(iv) || !(iv > 0.0f))
-            status = kErrEbRange;
-    }
-    *reinterpret_cast<float*>(out + kOffEbx2) = e2;
-    *reinterpret_cast<float*>(out + kOffInv) = iv;
-    *reinterpret_cast<float*>(out + kOffVmin) = flo;
-    *reinterpret_cast<float*>(out + kOffVmax) = fhi;
-    if (status) {
-        *reinterpret_cast<uint32_t*>(out + kOffStatus) = status;
-        *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off;
-    }
-    scr->pre_status = status;
+    params_field(out, g, eb, nparts);
 }
 
 // ----------------------------------------------------------------- launch
+int64_t minmax_blocks(int64_t n)
+{
+    int64_t blocks = (n / 4 + 255) / 256;
+    if (blocks > kMinmaxBlocks) blocks = kMinmaxBlocks;
+    return blocks < 1 ? 1 : blocks;
+}
+
 template <int RANK, bool VEC4>
 static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
@@ -771,9 +112,7 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
     if (e != hipSuccess) return e;
     if (rel) {
         const int64_t n = g.n[0] * g.n[1] * g.n[2];
-        int64_t blocks = (n / 4 + 255) / 256;
-        if (blocks > kMinmaxBlocks) blocks = kMinmaxBlocks;
-        if (blocks < 1) blocks = 1;
+        const int64_t blocks = minmax_blocks(n);
         hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, g, eb, (int)blocks);

@@ -1,0 +1,302 @@
+// fz_decompress_dev.hpp -- device code of the decompressor, shared by the
+// per-field kernel (fz_decompress.hip) and the batched one (fz_batch.hip).
+//
+// The inverse of the compression pass (Sec. 4.3 calls the two pipelines
+// symmetric).  One wave per chunk sweeps its steps in order.  Per step each
+// lane loads word t of its nonzero bricks (their positions follow from the bit
+// flags by popcount and mbcnt, Sec. 3.4) while the previous step is computed;
+// it undoes the bitshuffle with the same in-register transpose, decodes the
+// sign-magnitude codes (Sec. 3.2), and inverts the Lorenzo predictor as
+// inclusive prefix sums: along the patch in registers, across lanes for the
+// carries, and along the sweep dimension with the previous step kept in
+// registers.  Then it dequantizes (one fp32 multiply, Sec. 2.3) and stores.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fz_device.hpp"
+#include "fz_format.hpp"
+
+namespace fz {
+
+__device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank)
+{
+    const uint32_t w0 = *reinterpret_cast<const uint32_t*>(s + kOffMagic);
+    const uint32_t w1 = *reinterpret_cast<const uint32_t*>(s + kOffVersion);
+    if (w0 != kMagic) return 6;                                     // FZ_ERR_STREAM
+    if (w1 != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16))) return 7;  // FZ_ERR_VERSION
+    if (*reinterpret_cast<const uint32_t*>(s + kOffStatus) != 0u) return 8;    // FZ_ERR_STATUS
+    if (s[kOffDtype] != 0 || s[kOffRank] != rank) return 6;
+    for (int i = 0; i < 3; i++)
+        if (reinterpret_cast<const uint64_t*>(s + kOffDims)[i] != (uint64_t)g.n[i]) return 6;
+    if (*reinterpret_cast<const uint32_t*>(s + kOffNChunks) != (uint32_t)g.n_chunks) return 6;
+    const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
+    if (total < (uint64_t)g.payload_off || ((total - g.payload_off) & 15) != 0) return 6;
+    return 0;
+}
+
+__device__ __forceinline__ void decode_codes(const uint32_t (&P)[16], int (&d)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const uint32_t lo = P[i] & 0xFFFFu, hi = P[i] >> 16;
+        const int mlo = (int)(lo & 0x7FFFu), mhi = (int)(hi & 0x7FFFu);
+        d[i] = (lo & 0x8000u) ? -mlo : mlo;
+        d[i + 16] = (hi & 0x8000u) ? -mhi : mhi;
+    }
+}
+
+// Replace escaped cells (code 0x8000) by their logged deltas.  Pairs are in
+// code-index order: this step's pairs follow the `seen` earlier ones.
+__device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], int (&d)[32], const uint32_t* __restrict__ pairs,
+                                               uint32_t nout, uint32_t& seen, uint32_t n0, int lane)
+{
+    uint32_t emask = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        emask |= ((P[i] & 0xFFFFu) == kEscape ? 1u : 0u) << i;
+        emask |= ((P[i] >> 16) == kEscape ? 1u : 0u) << (i + 16);
+    }
+    const int cnt = __popc(emask);
+    const int incl = wave_incl_scan(cnt, lane);
+    const uint32_t total = (uint32_t)__shfl(incl, 63);
+    uint32_t pos = seen + (uint32_t)(incl - cnt);
+    uint32_t bad = 0;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if ((emask >> i) & 1u) {
+            if (pos < nout && pairs[2 * pos] == n0 + (uint32_t)lane * kPatchCodes + i) d[i] = (int)pairs[2 * pos + 1];
+            else bad = 1;
+            pos++;
+        }
+    }
+    seen += total;
+    return bad;
+}
+
+template <int CNT, bool VEC4>
+__device__ __forceinline__ void store_run(float* __restrict__ p, const int* q, float ebx2)
+{
+    if (VEC4) {
+#pragma unroll
+        for (int j = 0; j < CNT / 4; j++)
+            *reinterpret_cast<float4*>(p + 4 * j) = make_float4((float)q[4 * j] * ebx2, (float)q[4 * j + 1] * ebx2,
+                                                                (float)q[4 * j + 2] * ebx2, (float)q[4 * j + 3] * ebx2);
+    } else {
+#pragma unroll
+        for (int j = 0; j < CNT; j++) p[j] = (float)q[j] * ebx2;
+    }
+}
+
+template <int CNT>
+__device__ __forceinline__ void store_run_masked(float* __restrict__ p, const int* q, float ebx2, int valid)
+{
+#pragma unroll
+    for (int j = 0; j < CNT; j++)
+        if (j < valid) p[j] = (float)q[j] * ebx2;
+}
+
+// Decompress chunk c of a field with one wave (lane = 0..63).  A stream that
+// fails a check writes an fz_status code to *d_err (if given) and leaves the
+// chunk's output untouched.
+template <int RANK, bool VEC4>
+__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, float* __restrict__ y, const Geom& g,
+                                                 uint32_t* d_err, int64_t c, int lane)
+{
+    const uint32_t hdr_err = check_header(s, g, RANK);
+    if (hdr_err) {
+        if (c == 0 && lane == 0 && d_err) atomicCAS(d_err, 0u, hdr_err);
+        return;
+    }
+    const float ebx2 = *reinterpret_cast<const float*>(s + kOffEbx2);
+    const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
+    const uint64_t payload_units = (total - g.payload_off) / 16;
+    const uint32_t* tab = reinterpret_cast<const uint32_t*>(s + g.table_off + 8 * c);
+    const uint32_t off = tab[0], nout = tab[1];
+    const uint64_t* F = reinterpret_cast<const uint64_t*>(s + g.flags_off + (int64_t)kFlagBytesPerChunk * c);
+    int64_t org[3], ext[3];
+    chunk_box(g, c, org, ext);
+    const int L = layers_of(RANK, ext[0]);
+    uint32_t nnz = 0;
+    for (int i = 0; i < kLayers * kPlanes; i++) nnz += __popcll(F[i]);
+    bool bad = nout > (uint32_t)kChunkOutlierCap || (uint64_t)off + nnz + (nout + 1) / 2 > payload_units;
+    for (int i = L * kPlanes; i < kLayers * kPlanes; i++) bad |= F[i] != 0;
+    if (bad) {
+        if (lane == 0 && d_err) atomicCAS(d_err, 0u, 6u);
+        return;
+    }
+    bool edge = false;
+#pragma unroll
+    for (int i = 0; i < 3; i++) edge |= ext[i] < g.box[i];
+
+    const uint4* pay = reinterpret_cast<const uint4*>(s + g.payload_off);
+    const uint32_t* pairs = reinterpret_cast<const uint32_t*>(pay + off + nnz);
+    uint32_t seen = 0, esc_bad = 0;
+    // the chunk's bricks through a buffer resource based at its payload (reads
+    // past its nonzero bricks return 0, never another chunk's bytes)
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint4*>(pay + off), (short)0, (int)(16u * nnz), kBufferFlags);
+
+    // per-step brick words: plane b of this lane's brick holds word t of
+    // step 4k + t at byte voff[b] + 4t of the chunk's payload.  A zero brick
+    // gets an offset beyond the resource's range, where the load returns 0
+    // without touching memory: every load is issued unconditionally, so the
+    // wait for one step's words never has to cover the next step's loads.
+    constexpr uint32_t kZeroBrick = 0x80000000u;
+    uint32_t voff[16];
+    uint32_t cur = 0;
+    auto layer_offsets = [&](int k) {
+#pragma unroll
+        for (int b = 0; b < 16; b++) {
+            const uint64_t f = F[k * kPlanes + b];
+            voff[b] = ((f >> lane) & 1ull) ? 16u * (cur + mbcnt(f)) : kZeroBrick;
+            cur += (uint32_t)__popcll(f);
+        }
+    };
+    auto load_words = [&](int t, uint32_t (&w)[16]) {
+#pragma unroll
+        for (int b = 0; b < 16; b++) w[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[b] + 4u * t, 0u, 0);
+    };
+
+    // per-rank geometry of this lane's patch
+    const int py = lane & 7, px = lane >> 3;
+    int carry3[32];   // 3-D: previous plane's q of this patch
+    int carry2[16];   // 2-D: previous row's q of this patch
+    int carry1 = 0;   // 1-D: q just before the current step
+#pragma unroll
+    for (int i = 0; i < 32; i++) carry3[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) carry2[i] = 0;
+
+    uint32_t Wc[16];
+    layer_offsets(0);
+    load_words(0, Wc);
+    for (int k = 0; k < L; k++) {
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int st = 4 * k + t;
+            const int64_t step_lo = RANK == 3 ? st : RANK == 2 ? 2 * st : (int64_t)kStepCodes * st;
+            if (step_lo >= ext[0]) break;
+            // the next step's words are loaded while this step is computed
+            uint32_t Wn[16];
+            if (t < 3) {
+                load_words(t + 1, Wn);
+            } else if (k + 1 < L) {
+                layer_offsets(k + 1);
+                load_words(0, Wn);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t P[16];
+#pragma unroll
+            for (int b = 0; b < 16; b++) P[b] = Wc[b];
+            transpose16(P);
+            int d[32];
+            decode_codes(P, d);
+            if (nout) esc_bad |= apply_escapes(P, d, pairs, nout, seen, (uint32_t)st * kStepCodes, lane);
+
+            if (RANK == 3) {
+                // prefix along x inside the patch, carry across lanes lane-8, -16, -32
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int cc = 1; cc < 8; cc++) d[8 * r + cc] += d[8 * r + cc - 1];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int T = d[8 * r + 7];
+                    int inc = T;
+#pragma unroll
+                    for (int sh = 8; sh < 64; sh <<= 1) {
+                        const int tv = lane_value(inc, lane - sh);
+                        inc += lane >= sh ? tv : 0;
+                    }
+                    const int ex_ = inc - T;
+#pragma unroll
+                    for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += ex_;
+                }
+                // prefix along y inside the patch, carry across lanes -1, -2, -4
+#pragma unroll
+                for (int r = 1; r < 4; r++)
+#pragma unroll
+                    for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += d[8 * (r - 1) + cc];
+#pragma unroll
+                for (int cc = 0; cc < 8; cc++) {
+                    const int C = d[24 + cc];
+                    int inc = C;
+#pragma unroll
+                    for (int sh = 1; sh < 8; sh <<= 1) {
+                        const int tv = lane_value(inc, lane - sh);
+                        inc += py >= sh ? tv : 0;
+                    }
+                    const int ex_ = inc - C;
+#pragma unroll
+                    for (int r = 0; r < 4; r++) d[8 * r + cc] += ex_;
+                }
+                // prefix along z: previous plane of the same patch
+#pragma unroll
+                for (int i = 0; i < 32; i++) {
+                    d[i] += carry3[i];
+                    carry3[i] = d[i];
+                }
+                const int64_t z = org[0] + st, y0 = org[1] + 4 * py, x0 = org[2] + 8 * px;
+                if (edge) {
+                    const int ey = clampi(ext[1] - 4 * py, 0, 4), ex = clampi(ext[2] - 8 * px, 0, 8);
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+                        if (r < ey) store_run_masked<8>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, ex);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; r++) store_run<8, VEC4>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2);
+                }
+            } else if (RANK == 2) {
+#pragma unroll
+                for (int r = 0; r < 2; r++)
+#pragma unroll
+                    for (int cc = 1; cc < 16; cc++) d[16 * r + cc] += d[16 * r + cc - 1];
+#pragma unroll
+                for (int r = 0; r < 2; r++) {
+                    const int T = d[16 * r + 15];
+                    const int ex_ = wave_incl_scan(T, lane) - T;
+#pragma unroll
+                    for (int cc = 0; cc < 16; cc++) d[16 * r + cc] += ex_;
+                }
+#pragma unroll
+                for (int cc = 0; cc < 16; cc++) {
+                    d[cc] += carry2[cc];
+                    d[16 + cc] += d[cc];
+                    carry2[cc] = d[16 + cc];
+                }
+                const int64_t yy = org[0] + 2 * st, x0 = org[1] + 16 * lane;
+                if (edge) {
+                    const int ex = clampi(ext[1] - 16 * lane, 0, 16);
+                    store_run_masked<16>(y + (yy * g.n[1] + x0), d, ebx2, ex);
+                    if (2 * st + 1 < ext[0]) store_run_masked<16>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, ex);
+                } else {
+                    store_run<16, VEC4>(y + (yy * g.n[1] + x0), d, ebx2);
+                    store_run<16, VEC4>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2);
+                }
+            } else {
+#pragma unroll
+                for (int m = 1; m < 32; m++) d[m] += d[m - 1];
+                const int T = d[31];
+                const int ex_ = wave_incl_scan(T, lane) - T + carry1;
+#pragma unroll
+                for (int m = 0; m < 32; m++) d[m] += ex_;
+                carry1 = __builtin_amdgcn_readlane(d[31], 63);
+                const int64_t x0 = org[0] + (int64_t)kStepCodes * st + kPatchCodes * lane;
+                if (edge) {
+                    const int valid = clampi(ext[0] - ((int64_t)kStepCodes * st + kPatchCodes * lane), 0, 32);
+                    store_run_masked<32>(y + x0, d, ebx2, valid);
+                } else {
+                    store_run<32, VEC4>(y + x0, d, ebx2);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 16; b++) Wc[b] = Wn[b];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (nout && (esc_bad || seen != nout)) {
+        if (lane == 0 && d_err) atomicCAS(d_err, 0u, 6u);
+    }
+}
+
+}  // namespace fz

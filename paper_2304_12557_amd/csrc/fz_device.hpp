@@ -9,6 +9,11 @@
 
 namespace fz {
 
+// raw buffer resources: dword 3 of the descriptor (gfx9 data format 32); a
+// load at an offset of num_records bytes or more returns 0
+constexpr int kBufferFlags = 0x00020000;
+typedef uint32_t fz_u32x4 __attribute__((ext_vector_type(4)));
+
 // lane l receives lane l-1's value (DPP wave_shr:1).  Lane 0 receives an
 // unspecified value: the compiler may leave the DPP destination of a lane
 // without a source uninitialized, so callers mask it.

@@ -14,4 +14,11 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
                            hipStream_t st);
 hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);
 
+// blocks of the REL range pass of a field of n values
+int64_t minmax_blocks(int64_t n);
+// header image of a stream (magic, version, dims, eb, chunk box, ...)
+HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float inv);
+// eb parameters of an absolute bound; false if unusable
+bool abs_params(double eb, float* ebx2, float* inv);
+
 }  // namespace fz

@@ -91,3 +91,24 @@ def test_size_limits():
     assert bound(2, (32 << 16, (1 << 15) * 1024 - 1))[0] == 0  # contiguous extent too large first
     assert bound(3, (16 << 11, 32 << 10, 64 << 10))[0] == 0     # 2^31 chunks
     assert bound(3, (16 << 11, 32 << 10, (64 << 10) - 64))[0] > 0
+
+
+def test_batch_create_rejects_bad_jobs():
+    """Invalid jobs are refused before anything touches a device."""
+    L = fz.lib()
+    jobs = (fz.FzCompressJob * 2)()
+    for j in jobs:
+        j.d_in, j.d_out, j.eb, j.eb_mode = 16, 16, 1e-3, fz.FZ_EB_REL
+        j.dims = fz.dims_of((10, 10))
+    jobs[1].eb = -1.0
+    h = ctypes.c_void_p(123)
+    assert L.fz_batch_create_compress(2, jobs, ctypes.byref(h)) == 1
+    assert not h.value
+    jobs[1].eb, jobs[1].eb_mode = 1e-45, fz.FZ_EB_ABS
+    assert L.fz_batch_create_compress(2, jobs, ctypes.byref(h)) == 4
+    assert L.fz_batch_create_compress(0, jobs, ctypes.byref(h)) == 1
+    djobs = (fz.FzDecompressJob * 1)()
+    djobs[0].d_stream, djobs[0].d_out, djobs[0].dims = None, 16, fz.dims_of((5,))
+    assert L.fz_batch_create_decompress(1, djobs, ctypes.byref(h)) == 1
+    assert L.fz_batch_run(None, None) == 1
+    assert L.fz_batch_destroy(None) == 1

@@ -1,0 +1,131 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (the library chooses it from the field's shape).
+
+* 2-D climate-like 1800x3600 (REL 1e-4) and 3-D hurricane-like 100x500x500
+  (REL 1e-3, 1e-4): the whole stream byte for byte and the whole
+  reconstruction bit for bit against the oracle.
+* 3-D cosmology-like 512^3 (REL 1e-2, 1e-3, 1e-4), where the oracle's full run
+  would dominate the test time:
+  - the eb parameters against the oracle's own computation on the field;
+  - every reconstructed value against its closed form
+    fp32((float)rint(fp32(x*inv)) * ebx2) (the stages after prequantization
+    are lossless, Sec. 2.3 / 3.2-3.4), computed here in numpy;
+  - the size identities of the zero-block encoder (Sec. 3.4): total bytes =
+    header + 16 * (nonzero bricks + escape pairs / 2 rounded up), nonzero
+    bricks = popcount of all flags;
+  - a seeded sample of chunks (first, last and random ones) byte for byte:
+    the Lorenzo predictor is chunk-local, so the oracle compressing one
+    chunk's box alone, with the same eb parameters, must produce that chunk's
+    flags, escape count and payload.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2304_12557_amd as fz
+from oracle import oracle as O
+import stream_np
+import synth
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(os.cpu_count() or 1, 16)
+
+
+def run_gpu(x, eb, mode="rel"):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    buf = fz.compress(xt, eb, mode)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    y = fz.decompress(buf, x.shape, err=err)
+    torch.cuda.synchronize()
+    n = fz.stream_size(buf)
+    assert int(err.item()) == 0
+    return buf[:n].cpu().numpy(), y.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,eb", [("climate2d", 1e-4), ("hurricane3d", 1e-3), ("hurricane3d", 1e-4)])
+def test_whole_stream_full_size(name, eb):
+    x = getattr(synth, name)()
+    print("case", name, x.shape, eb, flush=True)
+    ref, st = O.compress(x, eb, O.EB_REL, threads=THREADS)
+    assert st == 0
+    s, y = run_gpu(x, eb)
+    assert s.size == ref.size, (s.size, ref.size)
+    if not np.array_equal(s, ref):
+        diff = np.nonzero(s != ref)[0]
+        raise AssertionError("stream differs at %d bytes, first at %d of %d" % (diff.size, diff[0], s.size))
+    yo, err = O.decompress(ref, x.shape)
+    assert err == 0
+    assert np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def cosmo():
+    return synth.lognormal3d(seed=300, n=512)
+
+
+def _geometry(shape):
+    box = stream_np.BOX[3]
+    grid = [-(-shape[i] // box[i]) for i in range(3)]
+    nch = grid[0] * grid[1] * grid[2]
+    table_off = 128
+    flags_off = table_off + -(-8 * nch // 16) * 16
+    payload_off = flags_off + 512 * nch
+    return box, grid, nch, table_off, flags_off, payload_off
+
+
+@pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
+def test_cosmology_512(cosmo, eb):
+    x = cosmo
+    print("case lognormal 512^3", eb, flush=True)
+    s, y = run_gpu(x, eb)
+    h = stream_np.header(s)
+    assert h["status"] == 0
+
+    # eb parameters (Sec. 4.1): the oracle's computation on the whole field
+    p = O.eb_params(x, eb, O.EB_REL)
+    assert p["status"] == 0
+    for k in ("ebx2", "inv", "vmin", "vmax"):
+        assert np.float32(h[k]).view(np.uint32) == np.float32(p[k]).view(np.uint32), k
+
+    # every value: the closed form of prequantization + dequantization
+    inv, ebx2 = np.float32(h["inv"]), np.float32(h["ebx2"])
+    q = np.rint(x * inv).astype(np.int32)
+    expect = q.astype(np.float32) * ebx2
+    bad = np.count_nonzero(y.view(np.uint32) != expect.view(np.uint32))
+    assert bad == 0, "%d reconstructed values differ from the closed form" % bad
+    del q, expect
+
+    # size identities of the zero-block encoder
+    box, grid, nch, table_off, flags_off, payload_off = _geometry(x.shape)
+    table = s[table_off:table_off + 8 * nch].view(np.uint32).reshape(nch, 2)
+    flags = s[flags_off:payload_off].view(np.uint64)
+    pop = int(np.unpackbits(flags.view(np.uint8)).sum())
+    assert h["nnz"] == pop
+    assert h["n_out"] == int(table[:, 1].sum())
+    per_chunk_flags = flags.reshape(nch, 64)
+    units = np.unpackbits(per_chunk_flags.view(np.uint8), axis=1).sum(axis=1).astype(np.int64) + (table[:, 1] + 1) // 2
+    assert h["total"] == payload_off + 16 * int(units.sum())
+    assert np.array_equal(table[:, 0].astype(np.int64), np.concatenate([[0], np.cumsum(units)[:-1]]))
+
+    # sampled chunks against the oracle on the chunk's box alone (ABS mode with
+    # the same eb_abs, hence the same ebx2 and inv)
+    eb_abs = eb * (float(h["vmax"]) - float(h["vmin"]))
+    rng = np.random.default_rng(12345)
+    sample = sorted(set([0, nch - 1, nch // 2] + list(rng.choice(nch, 21, replace=False))))
+    for c in sample:
+        cz, cy, cx = c // (grid[1] * grid[2]), (c // grid[2]) % grid[1], c % grid[2]
+        sub = np.ascontiguousarray(x[cz * box[0]:(cz + 1) * box[0], cy * box[1]:(cy + 1) * box[1],
+                                     cx * box[2]:(cx + 1) * box[2]])
+        ref, st = O.compress(sub, eb_abs, O.EB_ABS)
+        assert st == 0
+        hr = stream_np.header(ref)
+        assert np.float32(hr["ebx2"]) == ebx2 and np.float32(hr["inv"]) == inv
+        # one-chunk stream: header 128, table 16, flags 512, then the payload
+        assert np.array_equal(ref[144:656], s[flags_off + 512 * c:flags_off + 512 * (c + 1)]), c
+        rtab = ref[128:136].view(np.uint32)
+        assert rtab[1] == table[c, 1], c
+        start = payload_off + 16 * int(table[c, 0])
+        assert np.array_equal(ref[656:], s[start:start + ref.size - 656]), c
