@@ -176,6 +176,61 @@ int fz_batch_tune(fz_batch *b, void *stream);
 /* Free the plan's device tables (hipFree synchronizes the device). */
 int fz_batch_destroy(fz_batch *b);
 
+/* ------------------------------------------------------------- server
+ * A request loop on the current device: compress and decompress requests
+ * arrive from any host thread; a worker thread admits them in arrival order
+ * against an HBM budget (the device bytes each request holds while admitted)
+ * and launches the admitted ones in batches (the batch layer's kernels) on
+ * `slots` streams, so requests arriving while others run join the next batch
+ * as soon as a slot and budget free up, and batches on different streams
+ * overlap on the device.  Each result is exactly that of the per-field call.
+ * The caller owns the request buffers (device memory) and must keep them
+ * until fz_server_wait returns for that request.  The server allocates its
+ * streams, device table areas and pinned staging at creation, nothing per
+ * request. */
+#define FZ_REQ_COMPRESS 0
+#define FZ_REQ_DECOMPRESS 1
+
+typedef struct {
+    int32_t kind;        /* FZ_REQ_COMPRESS or FZ_REQ_DECOMPRESS */
+    int32_t eb_mode;     /* compress: FZ_EB_ABS or FZ_EB_REL */
+    double eb;           /* compress: the error bound */
+    fz_dims dims;
+    const void *d_in;    /* compress: N fp32 values; decompress: the stream */
+    void *d_out;         /* compress: fz_compress_bound bytes; decompress: N fp32 */
+    uint32_t *d_err;     /* decompress: optional error word, as for fz_decompress */
+    uint64_t hbm_bytes;  /* device bytes charged against the budget while admitted;
+                            0: 4N + fz_compress_bound(dims) */
+} fz_request;
+
+typedef struct {
+    uint64_t submitted, completed, queued;  /* queued: waiting for budget or a slot */
+    uint64_t batches;                       /* batch launches */
+    double mean_batch;                      /* requests per batch launch */
+    uint64_t admission_waits;               /* requests that waited for the budget */
+    uint64_t inflight_max_bytes;            /* high-water mark of admitted bytes */
+    uint64_t input_bytes;                   /* uncompressed bytes of completed requests */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submit -> completion, completed requests */
+    double wall_s;                          /* first submit -> last completion */
+} fz_server_report;
+
+typedef struct fz_server fz_server;
+
+/* hbm_budget > 0; slots in 1..16 (streams); max_batch in 1..4096. */
+int fz_server_create(uint64_t hbm_budget, int slots, int max_batch, fz_server **out);
+/* Validates the request (argument errors return at once; a request larger
+ * than the whole budget is FZ_ERR_ARG) and queues it; *ticket names it. */
+int fz_server_submit(fz_server *s, const fz_request *r, uint64_t *ticket);
+/* Blocks until the request is done; *status is FZ_OK or FZ_ERR_HIP.
+ * Data-dependent results are in the output as for the per-field calls. */
+int fz_server_wait(fz_server *s, uint64_t ticket, int *status);
+/* *done = 1 once the request is done (then fz_server_wait returns at once). */
+int fz_server_poll(fz_server *s, uint64_t ticket, int *done);
+int fz_server_stats(fz_server *s, fz_server_report *out);
+int fz_server_reset_stats(fz_server *s);
+/* Finishes every queued request, then frees the server. */
+int fz_server_destroy(fz_server *s);
+
 /* Parse a host copy of the first n >= 128 bytes of a stream. */
 int fz_stream_info(const void *h_header, size_t n, fz_info *out);
 

@@ -50,6 +50,20 @@ class FzDecompressJob(ctypes.Structure):
                 ("d_err", ctypes.c_void_p)]
 
 
+class FzRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("eb_mode", ctypes.c_int32), ("eb", ctypes.c_double), ("dims", FzDims),
+                ("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("d_err", ctypes.c_void_p),
+                ("hbm_bytes", ctypes.c_uint64)]
+
+
+class FzServerReport(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double), ("admission_waits", ctypes.c_uint64),
+                ("inflight_max_bytes", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
 class FzError(RuntimeError):
     def __init__(self, code, what=""):
         super().__init__("%s: %s (%d)" % (what, ERRORS.get(code, "unknown"), code))
@@ -87,13 +101,29 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.fz_batch_destroy.argtypes = [vp]
         L.fz_batch_destroy.restype = ctypes.c_int
+        L.fz_server_create.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, pp]
+        L.fz_server_create.restype = ctypes.c_int
+        L.fz_server_submit.argtypes = [vp, ctypes.POINTER(FzRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.fz_server_submit.restype = ctypes.c_int
+        L.fz_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.fz_server_wait.restype = ctypes.c_int
+        L.fz_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.fz_server_poll.restype = ctypes.c_int
+        L.fz_server_stats.argtypes = [vp, ctypes.POINTER(FzServerReport)]
+        L.fz_server_stats.restype = ctypes.c_int
+        for name in ("fz_server_reset_stats", "fz_server_destroy"):
+            getattr(L, name).argtypes = [vp]
+            getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
 
 SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
-           "fz_batch_destroy"]
+           "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
+           "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy"]
+FZ_REQ_COMPRESS = 0
+FZ_REQ_DECOMPRESS = 1
 
 
 def dims_of(shape):
@@ -260,6 +290,93 @@ class Batch:
             lib().fz_batch_destroy(self._h)
         self._h = None
         self._tensors = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The request server (continuous batching with HBM admission) on the
+    current device.  ``submit_compress`` / ``submit_decompress`` queue a
+    request and return a ticket; ``wait(ticket)`` blocks until it is done and
+    returns its output tensor.  Request tensors stay referenced until then."""
+
+    def __init__(self, hbm_budget, slots=4, max_batch=64):
+        h = ctypes.c_void_p()
+        rc = lib().fz_server_create(int(hbm_budget), int(slots), int(max_batch), ctypes.byref(h))
+        if rc:
+            raise FzError(rc, "fz_server_create")
+        self._h = h
+        self._live = {}
+
+    def _submit(self, req, keep, out):
+        t = ctypes.c_uint64()
+        rc = lib().fz_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if rc:
+            raise FzError(rc, "fz_server_submit")
+        self._live[t.value] = (keep, out)
+        return t.value
+
+    def submit_compress(self, x, eb, mode="rel", out=None, hbm_bytes=0):
+        import torch
+
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous float32 CUDA tensor")
+        dims = dims_of(x.shape)
+        bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
+        if out is None:
+            out = torch.empty(bound, dtype=torch.uint8, device=x.device)
+        elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
+            raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
+        r = FzRequest(kind=FZ_REQ_COMPRESS, eb_mode=_mode(mode), eb=float(eb), dims=dims, d_in=x.data_ptr(),
+                      d_out=out.data_ptr(), d_err=None, hbm_bytes=int(hbm_bytes))
+        return self._submit(r, [x, out], out)
+
+    def submit_decompress(self, s, shape, out=None, err=None, hbm_bytes=0):
+        import torch
+
+        if out is None:
+            out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
+        r = FzRequest(kind=FZ_REQ_DECOMPRESS, eb_mode=0, eb=0.0, dims=dims_of(shape), d_in=s.data_ptr(),
+                      d_out=out.data_ptr(), d_err=err.data_ptr() if err is not None else None,
+                      hbm_bytes=int(hbm_bytes))
+        return self._submit(r, [s, out, err], out)
+
+    def wait(self, ticket):
+        st = ctypes.c_int()
+        rc = lib().fz_server_wait(self._h, int(ticket), ctypes.byref(st))
+        if rc:
+            raise FzError(rc, "fz_server_wait")
+        _, out = self._live.pop(ticket)
+        if st.value:
+            raise FzError(st.value, "request %d" % ticket)
+        return out
+
+    def done(self, ticket):
+        d = ctypes.c_int()
+        rc = lib().fz_server_poll(self._h, int(ticket), ctypes.byref(d))
+        if rc:
+            raise FzError(rc, "fz_server_poll")
+        return bool(d.value)
+
+    def stats(self):
+        r = FzServerReport()
+        rc = lib().fz_server_stats(self._h, ctypes.byref(r))
+        if rc:
+            raise FzError(rc, "fz_server_stats")
+        return {f: getattr(r, f) for f, _ in FzServerReport._fields_}
+
+    def reset_stats(self):
+        lib().fz_server_reset_stats(self._h)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().fz_server_destroy(self._h)
+        self._h = None
+        self._live = {}
 
     def __del__(self):
         try:

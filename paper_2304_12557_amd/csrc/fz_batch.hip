@@ -28,34 +28,11 @@
 
 #include "fz.h"
 #include "fz_compress_dev.hpp"
+#include "fz_batch.hpp"
 #include "fz_decompress_dev.hpp"
 #include "fz_kernels.hpp"
 
 namespace fz {
-
-struct CompressJob {
-    const float* x;
-    uint8_t* out;
-    Geom g;
-    HeaderImage h;
-    double eb;
-    int32_t key;  // rank * 2 + (16-byte aligned rows ? 1 : 0)
-    int32_t rel;
-    int64_t chunk0;     // first ticket of this field in its class's part of the chunk table
-    int64_t chunkg;     // first entry of this field in the whole chunk table
-    int64_t mm0;        // first range-pass block of this field (REL)
-    int64_t mm_blocks;  // range-pass blocks of this field (REL)
-};
-
-struct DecompressJob {
-    const uint8_t* s;
-    float* y;
-    Geom g;
-    uint32_t* err;
-    int32_t key;
-    int32_t pad;
-    int64_t chunk0;
-};
 
 // ---------------------------------------------------------------- kernels
 __global__ __launch_bounds__(256) void k_batch_init(const CompressJob* __restrict__ jobs, int n_jobs,
@@ -175,31 +152,6 @@ __global__ __launch_bounds__(64) void k_batch_decompress(const DecompressJob* __
 }
 
 // ------------------------------------------------------------------- plans
-struct Tuning {
-    int per_cu;      // persistent compression workgroups per CU (1 or 2)
-    int mm_cap;      // range-pass blocks per field, at most
-    int move_threads;
-};
-
-struct Plan {
-    bool compress;
-    int n_jobs;
-    int64_t total_chunks;
-    int64_t class_off[8], class_chunks[8];  // compression: the chunk table is ordered by class (key)
-    int64_t total_mm;
-    int64_t mm_max;  // range-pass blocks with the largest per-field cap
-    bool any_rel;
-    int cus;
-    Tuning tune;
-    std::vector<CompressJob> cjobs;
-    std::vector<DecompressJob> djobs;
-    void* dev;  // device block: ticket, job table, chunk -> job, block -> job
-    uint32_t* d_ticket;
-    void* d_jobs;
-    int32_t* d_chunk_job;
-    int32_t* d_mm_job;
-};
-
 namespace {
 
 int vec_key(const void* p, const Geom& g)
@@ -208,8 +160,20 @@ int vec_key(const void* p, const Geom& g)
     return g.rank * 2 + (vec4 ? 1 : 0);
 }
 
-// (Re)build the device tables of a plan for its current tuning.
-int upload(Plan* P)
+int cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 1;
+    return cus;
+}
+
+}  // namespace
+
+// Host image of a plan's device tables for its current tuning: ticket
+// counters, job table, chunk -> job, range-pass block -> job.  `cap_mm` is
+// the number of block entries reserved (at least the current count).
+size_t plan_layout(Plan* P, int64_t cap_mm, std::vector<uint8_t>* img)
 {
     std::vector<int32_t> chunk_job(P->total_chunks), mm_job;
     int64_t mm = 0;
@@ -232,41 +196,50 @@ int upload(Plan* P)
         }
     }
     P->total_mm = mm;
-    // one device block, sized for the largest tuning (its addresses never
-    // change, so launches captured in a graph stay valid until the plan is
-    // destroyed; tune before capturing, since a capture bakes the tuning in)
+    if (cap_mm < mm) cap_mm = mm;
     const size_t job_bytes = P->compress ? sizeof(CompressJob) * P->n_jobs : sizeof(DecompressJob) * P->n_jobs;
-    const size_t off_jobs = 256;
-    const size_t off_chunk = (off_jobs + job_bytes + 255) / 256 * 256;
-    const size_t off_mm = (off_chunk + 4 * (size_t)P->total_chunks + 255) / 256 * 256;
-    const size_t bytes = off_mm + 4 * (size_t)(P->mm_max > 0 ? P->mm_max : 1);
+    P->off_jobs = 256;
+    P->off_chunk = (P->off_jobs + job_bytes + 255) / 256 * 256;
+    P->off_mm = (P->off_chunk + 4 * (size_t)P->total_chunks + 255) / 256 * 256;
+    const size_t bytes = P->off_mm + 4 * (size_t)(cap_mm > 0 ? cap_mm : 1);
+    if (img) {
+        img->assign(bytes, 0);
+        const void* src =
+            P->compress ? static_cast<const void*>(P->cjobs.data()) : static_cast<const void*>(P->djobs.data());
+        std::memcpy(img->data() + P->off_jobs, src, job_bytes);
+        std::memcpy(img->data() + P->off_chunk, chunk_job.data(), 4 * chunk_job.size());
+        if (mm > 0) std::memcpy(img->data() + P->off_mm, mm_job.data(), 4 * mm_job.size());
+    }
+    return bytes;
+}
+
+// Point the plan at a device area that holds (or will hold) its image.
+void plan_bind(Plan* P, void* dev)
+{
+    uint8_t* base = static_cast<uint8_t*>(dev);
+    P->d_ticket = reinterpret_cast<uint32_t*>(base);
+    P->d_jobs = base + P->off_jobs;
+    P->d_chunk_job = reinterpret_cast<int32_t*>(base + P->off_chunk);
+    P->d_mm_job = reinterpret_cast<int32_t*>(base + P->off_mm);
+}
+
+// (Re)build the device tables of a standalone plan for its current tuning:
+// one device block, sized for the largest tuning (its addresses never change,
+// so launches captured in a graph stay valid until the plan is destroyed;
+// tune before capturing, since a capture bakes the tuning in).
+int upload(Plan* P)
+{
+    std::vector<uint8_t> img;
+    const size_t bytes = plan_layout(P, P->mm_max, &img);
     if (!P->dev && hipMalloc(&P->dev, bytes) != hipSuccess) {
         P->dev = nullptr;
         return FZ_ERR_HIP;
     }
-    uint8_t* base = static_cast<uint8_t*>(P->dev);
-    P->d_ticket = reinterpret_cast<uint32_t*>(base);
-    P->d_jobs = base + off_jobs;
-    P->d_chunk_job = reinterpret_cast<int32_t*>(base + off_chunk);
-    P->d_mm_job = reinterpret_cast<int32_t*>(base + off_mm);
-    const void* src = P->compress ? static_cast<const void*>(P->cjobs.data()) : static_cast<const void*>(P->djobs.data());
-    if (hipMemcpy(P->d_jobs, src, job_bytes, hipMemcpyHostToDevice) != hipSuccess) return FZ_ERR_HIP;
-    if (hipMemcpy(P->d_chunk_job, chunk_job.data(), 4 * chunk_job.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return FZ_ERR_HIP;
-    if (mm > 0 && hipMemcpy(P->d_mm_job, mm_job.data(), 4 * mm_job.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return FZ_ERR_HIP;
-    return FZ_OK;
+    plan_bind(P, P->dev);
+    return hipMemcpy(P->dev, img.data(), bytes, hipMemcpyHostToDevice) == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
-int cu_count()
-{
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 1;
-    return cus;
-}
-
-hipError_t run(const Plan* P, hipStream_t st)
+hipError_t plan_run(const Plan* P, hipStream_t st)
 {
     hipError_t e;
     if (!P->compress) {
@@ -309,26 +282,10 @@ hipError_t run(const Plan* P, hipStream_t st)
     return hipGetLastError();
 }
 
-}  // namespace
-
-}  // namespace fz
-
-using namespace fz;
-
-struct fz_batch {
-    Plan p;
-};
-
-extern "C" {
-
-int fz_batch_create_compress(int n, const fz_compress_job* jobs, fz_batch** out)
+int plan_compress(Plan* Pp, int n, const fz_compress_job* jobs)
 {
-    if (!out) return FZ_ERR_ARG;
-    *out = nullptr;
+    Plan& P = *Pp;
     if (n < 1 || !jobs) return FZ_ERR_ARG;
-    fz_batch* b = new (std::nothrow) fz_batch();
-    if (!b) return FZ_ERR_ARG;
-    Plan& P = b->p;
     P.compress = true;
     P.n_jobs = n;
     for (int k = 0; k < 8; k++) P.class_off[k] = P.class_chunks[k] = 0;
@@ -337,22 +294,18 @@ int fz_batch_create_compress(int n, const fz_compress_job* jobs, fz_batch** out)
     P.tune = Tuning{2, kMinmaxBlocks, 256};
     P.any_rel = false;
     P.mm_max = 0;
+    P.cjobs.clear();
+    P.djobs.clear();
     int64_t chunks = 0;
     for (int i = 0; i < n; i++) {
         const fz_compress_job& q = jobs[i];
         CompressJob J;
         std::memset(&J, 0, sizeof(J));
         const double eb = q.eb;
-        int status = FZ_OK;
-        if (!q.d_in || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) status = FZ_ERR_ARG;
-        else if (!(eb > 0.0) || !std::isfinite(eb) || (q.eb_mode != FZ_EB_ABS && q.eb_mode != FZ_EB_REL))
-            status = FZ_ERR_ARG;
+        if (!q.d_in || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) return FZ_ERR_ARG;
+        if (!(eb > 0.0) || !std::isfinite(eb) || (q.eb_mode != FZ_EB_ABS && q.eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
         float ebx2 = 0.0f, inv = 0.0f;
-        if (status == FZ_OK && q.eb_mode == FZ_EB_ABS && !abs_params(eb, &ebx2, &inv)) status = FZ_ERR_EB_RANGE;
-        if (status != FZ_OK) {
-            delete b;
-            return status;
-        }
+        if (q.eb_mode == FZ_EB_ABS && !abs_params(eb, &ebx2, &inv)) return FZ_ERR_EB_RANGE;
         J.x = q.d_in;
         J.out = static_cast<uint8_t*>(q.d_out);
         J.h = header_image(J.g, eb, q.eb_mode, ebx2, inv);
@@ -366,10 +319,7 @@ int fz_batch_create_compress(int n, const fz_compress_job* jobs, fz_batch** out)
         if (J.rel) P.mm_max += minmax_blocks(J.g.n[0] * J.g.n[1] * J.g.n[2]);
         P.cjobs.push_back(J);
     }
-    if (chunks >= (1ll << 31)) {
-        delete b;
-        return FZ_ERR_ARG;
-    }
+    if (chunks >= (1ll << 31)) return FZ_ERR_ARG;
     P.total_chunks = chunks;
     int64_t off = 0;
     for (int key = 0; key < 8; key++) {  // the chunk table is ordered by class
@@ -377,24 +327,13 @@ int fz_batch_create_compress(int n, const fz_compress_job* jobs, fz_batch** out)
         off += P.class_chunks[key];
     }
     for (CompressJob& J : P.cjobs) J.chunkg = P.class_off[J.key] + J.chunk0;
-    const int rc = upload(&P);
-    if (rc != FZ_OK) {
-        if (P.dev) (void)hipFree(P.dev);
-        delete b;
-        return rc;
-    }
-    *out = b;
     return FZ_OK;
 }
 
-int fz_batch_create_decompress(int n, const fz_decompress_job* jobs, fz_batch** out)
+int plan_decompress(Plan* Pp, int n, const fz_decompress_job* jobs)
 {
-    if (!out) return FZ_ERR_ARG;
-    *out = nullptr;
+    Plan& P = *Pp;
     if (n < 1 || !jobs) return FZ_ERR_ARG;
-    fz_batch* b = new (std::nothrow) fz_batch();
-    if (!b) return FZ_ERR_ARG;
-    Plan& P = b->p;
     P.compress = false;
     P.n_jobs = n;
     for (int k = 0; k < 8; k++) P.class_off[k] = P.class_chunks[k] = 0;
@@ -403,15 +342,14 @@ int fz_batch_create_decompress(int n, const fz_decompress_job* jobs, fz_batch** 
     P.tune = Tuning{2, kMinmaxBlocks, 256};
     P.any_rel = false;
     P.mm_max = 0;
+    P.cjobs.clear();
+    P.djobs.clear();
     int64_t chunks = 0;
     for (int i = 0; i < n; i++) {
         const fz_decompress_job& q = jobs[i];
         DecompressJob J;
         std::memset(&J, 0, sizeof(J));
-        if (!q.d_stream || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) {
-            delete b;
-            return FZ_ERR_ARG;
-        }
+        if (!q.d_stream || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) return FZ_ERR_ARG;
         J.s = static_cast<const uint8_t*>(q.d_stream);
         J.y = q.d_out;
         J.err = q.d_err;
@@ -420,14 +358,32 @@ int fz_batch_create_decompress(int n, const fz_decompress_job* jobs, fz_batch** 
         chunks += J.g.n_chunks;
         P.djobs.push_back(J);
     }
-    if (chunks >= (1ll << 31)) {
-        delete b;
-        return FZ_ERR_ARG;
-    }
+    if (chunks >= (1ll << 31)) return FZ_ERR_ARG;
     P.total_chunks = chunks;
-    const int rc = upload(&P);
+    return FZ_OK;
+}
+
+}  // namespace fz
+
+using namespace fz;
+
+struct fz_batch {
+    Plan p;
+};
+
+namespace {
+
+int create(fz_batch** out, bool compress, int n, const void* jobs)
+{
+    if (!out) return FZ_ERR_ARG;
+    *out = nullptr;
+    fz_batch* b = new (std::nothrow) fz_batch();
+    if (!b) return FZ_ERR_ARG;
+    int rc = compress ? plan_compress(&b->p, n, static_cast<const fz_compress_job*>(jobs))
+                      : plan_decompress(&b->p, n, static_cast<const fz_decompress_job*>(jobs));
+    if (rc == FZ_OK) rc = upload(&b->p);
     if (rc != FZ_OK) {
-        if (P.dev) (void)hipFree(P.dev);
+        if (b->p.dev) (void)hipFree(b->p.dev);
         delete b;
         return rc;
     }
@@ -435,10 +391,24 @@ int fz_batch_create_decompress(int n, const fz_decompress_job* jobs, fz_batch** 
     return FZ_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int fz_batch_create_compress(int n, const fz_compress_job* jobs, fz_batch** out)
+{
+    return create(out, true, n, jobs);
+}
+
+int fz_batch_create_decompress(int n, const fz_decompress_job* jobs, fz_batch** out)
+{
+    return create(out, false, n, jobs);
+}
+
 int fz_batch_run(fz_batch* b, void* stream)
 {
     if (!b) return FZ_ERR_ARG;
-    return run(&b->p, static_cast<hipStream_t>(stream)) == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+    return plan_run(&b->p, static_cast<hipStream_t>(stream)) == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
 int fz_batch_tune(fz_batch* b, void* stream)
@@ -461,11 +431,11 @@ int fz_batch_tune(fz_batch* b, void* stream)
     for (const Tuning& t : cands) {
         P.tune = t;
         if ((rc = upload(&P)) != FZ_OK) break;
-        if (run(&P, st) != hipSuccess) { rc = FZ_ERR_HIP; break; }  // warm-up
+        if (plan_run(&P, st) != hipSuccess) { rc = FZ_ERR_HIP; break; }  // warm-up
         float ms = 1e30f;
         for (int r = 0; r < 3 && rc == FZ_OK; r++) {
             float m = 0.0f;
-            if (hipEventRecord(e0, st) != hipSuccess || run(&P, st) != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+            if (hipEventRecord(e0, st) != hipSuccess || plan_run(&P, st) != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&m, e0, e1) != hipSuccess)
                 rc = FZ_ERR_HIP;
             ms = m < ms ? m : ms;

@@ -112,3 +112,17 @@ def test_batch_create_rejects_bad_jobs():
     assert L.fz_batch_create_decompress(1, djobs, ctypes.byref(h)) == 1
     assert L.fz_batch_run(None, None) == 1
     assert L.fz_batch_destroy(None) == 1
+
+
+def test_server_argument_errors():
+    """Server calls refuse bad arguments without touching a device."""
+    L = fz.lib()
+    h = ctypes.c_void_p(7)
+    assert L.fz_server_create(0, 2, 8, ctypes.byref(h)) == 1 and not h.value
+    assert L.fz_server_create(1 << 30, 0, 8, ctypes.byref(h)) == 1
+    assert L.fz_server_create(1 << 30, 2, 0, ctypes.byref(h)) == 1
+    t = ctypes.c_uint64()
+    r = fz.FzRequest(kind=0, eb_mode=1, eb=1e-3, dims=fz.dims_of((10,)), d_in=16, d_out=16, d_err=None, hbm_bytes=0)
+    assert L.fz_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == 1
+    assert L.fz_server_wait(None, 1, None) == 1
+    assert L.fz_server_destroy(None) == 1
