@@ -35,6 +35,10 @@ def parse():
     p.add_argument("--seed", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU time of the oracle baseline")
+    p.add_argument("--no-layers", action="store_true", help="skip the batched and serving measurements")
+    p.add_argument("--batch-fields", type=int, default=256)
+    p.add_argument("--serve-requests", type=int, default=2000, help="requests per offered-load level")
+    p.add_argument("--serve-seconds", type=float, default=4.0, help="longest trace per offered-load level")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run one plain elementwise copy of the field (4N bytes read, 4N written) before the timed "
                         "region: the reference dispatch that scales the HBM counters of a profiling run")
@@ -105,6 +109,257 @@ def cpu_baseline(x, eb, min_seconds):
                       x.shape[0], x.shape[1], x.shape[2], reps, threads, tc / reps, td / reps),
     }
 
+
+
+def event_ms(fn, stream, reps):
+    """Median over `reps` of the device time of fn() on `stream` (ms)."""
+    import numpy as np
+    import torch
+
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def bench_batched(n_fields, reps=5):
+    """The batch layer on 256 mixed-rank fields (16 KiB - 64 MiB, log-uniform,
+    sine workload, REL eb drawn from {1e-2, 1e-3, 1e-4}): one plan run replayed
+    from a graph against the same fields as plain per-field calls on one stream.
+    GB/s over input bytes."""
+    import torch
+
+    import paper_2304_12557_amd as fz
+    import synth
+
+    dev = torch.device("cuda:0")
+    shapes = synth.batch_shapes(n_fields=n_fields, seed=3000)
+    xs = [synth.sine_field_device(sh, 3000 + i, dev) for i, sh in enumerate(shapes)]
+    ebs = [synth.rel_eb_choice(3000 + i) for i in range(len(shapes))]
+    nbytes = sum(4 * x.numel() for x in xs)
+    st = torch.cuda.current_stream()
+    plain_out = [torch.empty(fz.compress_bound(x.shape), dtype=torch.uint8, device=dev) for x in xs]
+    batch_out = [torch.empty_like(o) for o in plain_out]
+
+    def plain_c():
+        for x, eb, o in zip(xs, ebs, plain_out):
+            fz.compress(x, eb, "rel", out=o)
+
+    plain_c()
+    t_plain_c = event_ms(plain_c, st, reps)
+    plan = fz.Batch.compress([(x, eb, "rel", o) for x, eb, o in zip(xs, ebs, batch_out)])
+    plan.tune()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        plan.run(stream=side)
+    g.replay()
+    torch.cuda.synchronize()
+    t_batch_c = event_ms(g.replay, st, reps)
+    same = all(fz.stream_size(a) == fz.stream_size(b) for a, b in zip(plain_out, batch_out))
+    same = same and all(torch.equal(plain_out[i][:fz.stream_size(plain_out[i])], batch_out[i][:fz.stream_size(batch_out[i])])
+                        for i in range(0, len(xs), 17))
+    s_bytes = sum(fz.stream_size(o) for o in plain_out)
+
+    ys_p = [torch.empty_like(x) for x in xs]
+    ys_b = [torch.empty_like(x) for x in xs]
+
+    def plain_d():
+        for o, x, y in zip(plain_out, xs, ys_p):
+            fz.decompress(o, x.shape, out=y)
+
+    plain_d()
+    t_plain_d = event_ms(plain_d, st, reps)
+    dplan = fz.Batch.decompress([(o, x.shape, y, None) for o, x, y in zip(batch_out, xs, ys_b)])
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=side):
+        dplan.run(stream=side)
+    g2.replay()
+    torch.cuda.synchronize()
+    t_batch_d = event_ms(g2.replay, st, reps)
+    same = same and all(torch.equal(ys_p[i].view(torch.int32), ys_b[i].view(torch.int32)) for i in range(0, len(xs), 17))
+    del g, g2
+    plan.close()
+    dplan.close()
+    gb = nbytes / 1e9
+    return {
+        "workload": "%d mixed-rank fields, 16 KiB-64 MiB log-uniform, sine workload, REL eb in {1e-2,1e-3,1e-4}"
+                    % len(xs),
+        "input_bytes": nbytes, "ratio": round(nbytes / s_bytes, 3), "identical_to_plain": bool(same),
+        "compress": {"batched_GBps": round(gb / (t_batch_c * 1e-3), 1), "plain_GBps": round(gb / (t_plain_c * 1e-3), 1),
+                     "batched_ms": round(t_batch_c, 3), "plain_ms": round(t_plain_c, 3)},
+        "decompress": {"batched_GBps": round(gb / (t_batch_d * 1e-3), 1), "plain_GBps": round(gb / (t_plain_d * 1e-3), 1),
+                       "batched_ms": round(t_batch_d, 3), "plain_ms": round(t_plain_d, 3)},
+        "tuning_note": "launch shapes from fz_batch_tune; plan run replayed from a graph",
+    }
+
+
+def bench_serving(n_requests, max_seconds, n_pool=48, seed=4000):
+    """The request server on a Poisson stream of requests (70 % compress, 30 %
+    decompress) over a pool of sine-workload fields with sizes log-uniform in
+    64 KiB - 256 MiB, at 25/50/90 % of the batched capacity measured on that
+    pool, with a 64 GiB admission budget; against plain per-request launches on
+    one stream fed by the same arrival trace.  Latency = arrival to completion
+    seen by the host."""
+    import ctypes
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2304_12557_amd as fz
+    import synth
+
+    dev = torch.device("cuda:0")
+    shapes = synth.batch_shapes(n_fields=n_pool, seed=seed, lo=64 << 10, hi=256 << 20)
+    xs = [synth.sine_field_device(sh, seed + i, dev) for i, sh in enumerate(shapes)]
+    ebs = [synth.rel_eb_choice(seed + i) for i in range(len(xs))]
+    streams = [fz.compress(x, eb, "rel") for x, eb in zip(xs, ebs)]
+    torch.cuda.synchronize()
+    # capacity: the whole pool as one batch (compress), bytes per second
+    outs = [torch.empty_like(s) for s in streams]
+    plan = fz.Batch.compress([(x, eb, "rel", o) for x, eb, o in zip(xs, ebs, outs)])
+    st = torch.cuda.current_stream()
+    plan.run()
+    t_cap = event_ms(plan.run, st, 3)
+    plan.close()
+    del outs
+    pool_bytes = sum(4 * x.numel() for x in xs)
+    capacity = pool_bytes / (t_cap * 1e-3)
+    mean_req = pool_bytes / len(xs)
+
+    def trace(load, rs):
+        rate = load * capacity / mean_req  # requests per second
+        t, out = 0.0, []
+        while len(out) < n_requests and t < max_seconds:
+            t += rs.exponential(1.0 / rate)
+            out.append((t, int(rs.integers(0, len(xs))), bool(rs.random() < 0.7)))
+        return out
+
+    def pctl(v, p):
+        v = sorted(v)
+        return v[min(len(v) - 1, max(0, int(np.ceil(p * len(v))) - 1))]
+
+    L = fz.lib()
+    bounds = [fz.compress_bound(x.shape) for x in xs]
+
+    def prebuilt(tr):
+        """Request structs and output buffers of a trace, made before timing."""
+        reqs, keep = [], []
+        for at, i, comp in tr:
+            dims = fz.dims_of(xs[i].shape)
+            if comp:
+                o = torch.empty(bounds[i], dtype=torch.uint8, device=dev)
+                r = fz.FzRequest(kind=fz.FZ_REQ_COMPRESS, eb_mode=fz.FZ_EB_REL, eb=float(ebs[i]), dims=dims,
+                                 d_in=xs[i].data_ptr(), d_out=o.data_ptr(), d_err=None, hbm_bytes=0)
+            else:
+                o = torch.empty_like(xs[i])
+                r = fz.FzRequest(kind=fz.FZ_REQ_DECOMPRESS, eb_mode=0, eb=0.0, dims=dims,
+                                 d_in=streams[i].data_ptr(), d_out=o.data_ptr(), d_err=None, hbm_bytes=0)
+            reqs.append(r)
+            keep.append(o)
+        torch.cuda.synchronize()
+        return reqs, keep
+
+    def spin_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            if d > 2e-3:
+                time.sleep(d - 1e-3)
+
+    def run_server(tr):
+        reqs, keep = prebuilt(tr)
+        srv = fz.Server(hbm_budget=64 << 30, slots=4, max_batch=64)
+        h = srv._h
+        tk = ctypes.c_uint64()
+        tickets = []
+        t0 = time.perf_counter()
+        for (at, _, _), r in zip(tr, reqs):
+            spin_until(t0 + at)
+            rc = L.fz_server_submit(h, ctypes.byref(r), ctypes.byref(tk))
+            assert rc == 0
+            tickets.append(tk.value)
+        stt = ctypes.c_int()
+        for t in tickets:
+            L.fz_server_wait(h, t, ctypes.byref(stt))
+            assert stt.value == 0
+        s = srv.stats()
+        srv.close()
+        del keep
+        return {"p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+                "GBps": round(s["input_bytes"] / 1e9 / max(s["wall_s"], 1e-9), 1),
+                "mean_batch": round(s["mean_batch"], 2), "admission_waits": int(s["admission_waits"])}
+
+    def run_plain(tr):
+        reqs, keep = prebuilt(tr)
+        lat, done_t = [], []
+        pend = []
+        lock = threading.Condition()
+        finished = [False]
+
+        def poller():
+            while True:
+                with lock:
+                    while not pend and not finished[0]:
+                        lock.wait()
+                    if not pend and finished[0]:
+                        return
+                    ev, arrival = pend[0]
+                while not ev.query():
+                    time.sleep(2e-5)
+                now = time.perf_counter()
+                with lock:
+                    pend.pop(0)
+                    lat.append((now - arrival) * 1e3)
+                    done_t.append(now)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        stream = torch.cuda.Stream()
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        evs = [torch.cuda.Event() for _ in tr]
+        t0 = time.perf_counter()
+        for (at, _, _), r, ev in zip(tr, reqs, evs):
+            spin_until(t0 + at)
+            if r.kind == fz.FZ_REQ_COMPRESS:
+                rc = L.fz_compress(ctypes.c_void_p(r.d_in), ctypes.byref(r.dims), r.eb, r.eb_mode,
+                                   ctypes.c_void_p(r.d_out), sp)
+            else:
+                rc = L.fz_decompress(ctypes.c_void_p(r.d_in), ctypes.c_void_p(r.d_out), ctypes.byref(r.dims), None, sp)
+            assert rc == 0
+            ev.record(stream)
+            with lock:
+                pend.append((ev, t0 + at))
+                lock.notify()
+        with lock:
+            finished[0] = True
+            lock.notify()
+        th.join()
+        torch.cuda.synchronize()
+        del keep
+        nbytes = sum(4 * xs[i].numel() for _, i, _ in tr)
+        wall = max(done_t) - (t0 + tr[0][0])
+        return {"p50_ms": round(pctl(lat, 0.50), 3), "p99_ms": round(pctl(lat, 0.99), 3),
+                "GBps": round(nbytes / 1e9 / max(wall, 1e-9), 1)}
+
+    levels = []
+    for k, load in enumerate((0.25, 0.5, 0.9)):
+        tr = trace(load, np.random.default_rng(seed + 100 + k))
+        levels.append({"offered_load": load, "requests": len(tr), "served": run_server(tr), "plain": run_plain(tr)})
+    return {
+        "workload": "Poisson stream, 70/30 compress/decompress, %d sine fields 64 KiB-256 MiB log-uniform, "
+                    "64 GiB admission budget, 4 slots" % len(xs),
+        "batched_capacity_GBps": round(capacity / 1e9, 1), "levels": levels,
+    }
 
 def main():
     a = parse()
@@ -203,6 +458,12 @@ def main():
                      "traffic": measured_traffic(name, shape, a.eb),
                      "algorithmic_bytes": int(alg), "avg_launch_ms": round(t_ms, 4)},
     }
+    if not a.no_layers:
+        del buf, y
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(a.batch_fields)
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving(a.serve_requests, a.serve_seconds)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, a.eb, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -54,6 +54,37 @@ def sine_field(shape, seed, noise=1e-3):
     return f.astype(np.float32)
 
 
+def sine_field_device(shape, seed, device, noise=1e-3):
+    """The sine workload generated on a torch device (for benchmarks that need
+    gigabytes of fields quickly): the same seeded draws as sine_field for the
+    mode parameters, the sum computed in float32 on the device and torch's
+    own seeded normal noise, so values follow the same recipe but are not
+    bit-identical to sine_field's."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in shape)
+    rank = len(shape)
+    coords = [torch.arange(n, dtype=torch.float32, device=device).view(*[n if d == i else 1 for d in range(rank)])
+              for i, n in enumerate(shape)]
+    f = torch.zeros(shape, dtype=torch.float32, device=device)
+    for _ in range(8):
+        amp = rng.uniform(0.5, 1.0)
+        wl = rng.uniform(8.0, 64.0)
+        k = rng.normal(size=rank)
+        k /= np.linalg.norm(k)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        arg = torch.full((1,) * rank, float(ph), dtype=torch.float32, device=device)
+        for d in range(rank):
+            arg = arg + float(2.0 * np.pi / wl * k[d]) * coords[d]
+        f += float(amp) * torch.sin(arg)
+    if noise:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed))
+        f += noise * torch.randn(shape, generator=g, device=device, dtype=torch.float32)
+    return f.contiguous()
+
+
 def sine3d(seed=0, shape=(64, 64, 64)):
     return sine_field(shape, seed)
 
