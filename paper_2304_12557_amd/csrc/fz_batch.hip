@@ -138,16 +138,17 @@ __global__ __launch_bounds__(256) void k_batch_clear_err(const DecompressJob* __
 __global__ __launch_bounds__(64) void k_batch_decompress(const DecompressJob* __restrict__ jobs,
                                                          const int32_t* __restrict__ chunk_job)
 {
+    __shared__ float tile[kTileFloats];
     const DecompressJob& J = jobs[chunk_job[blockIdx.x]];
     const int64_t c = (int64_t)blockIdx.x - J.chunk0;
     const int lane = threadIdx.x;
     switch (J.key) {
-        case 7: decompress_chunk<3, true>(J.s, J.y, J.g, J.err, c, lane); break;
-        case 6: decompress_chunk<3, false>(J.s, J.y, J.g, J.err, c, lane); break;
-        case 5: decompress_chunk<2, true>(J.s, J.y, J.g, J.err, c, lane); break;
-        case 4: decompress_chunk<2, false>(J.s, J.y, J.g, J.err, c, lane); break;
-        case 3: decompress_chunk<1, true>(J.s, J.y, J.g, J.err, c, lane); break;
-        default: decompress_chunk<1, false>(J.s, J.y, J.g, J.err, c, lane); break;
+        case 7: decompress_chunk<3, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 6: decompress_chunk<3, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 5: decompress_chunk<2, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 4: decompress_chunk<2, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 3: decompress_chunk<1, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        default: decompress_chunk<1, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
     }
 }
 

@@ -11,7 +11,8 @@ template <int RANK, bool VEC4>
 __global__ __launch_bounds__(64) void k_decompress(const uint8_t* __restrict__ s, float* __restrict__ y, Geom g,
                                                    uint32_t* d_err)
 {
-    decompress_chunk<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x);
+    __shared__ float tile[kTileFloats];
+    decompress_chunk<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v)

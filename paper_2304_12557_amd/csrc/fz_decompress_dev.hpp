@@ -95,12 +95,17 @@ __device__ __forceinline__ void store_run_masked(float* __restrict__ p, const in
         if (j < valid) p[j] = (float)q[j] * ebx2;
 }
 
-// Decompress chunk c of a field with one wave (lane = 0..63).  A stream that
-// fails a check writes an fz_status code to *d_err (if given) and leaves the
-// chunk's output untouched.
+// Decompress chunk c of a field with one wave (lane = 0..63; the workgroup is
+// that one wave).  `tile` is kTileFloats of LDS.  A stream that fails a check
+// writes an fz_status code to *d_err (if given) and leaves the chunk's output
+// untouched.
+// LDS tile of one 3-D step (32 rows of 64 values, padded against bank conflicts)
+constexpr int kTilePitch = 68;
+constexpr int kTileFloats = 32 * kTilePitch;
+
 template <int RANK, bool VEC4>
 __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, float* __restrict__ y, const Geom& g,
-                                                 uint32_t* d_err, int64_t c, int lane)
+                                                 uint32_t* d_err, int64_t c, int lane, float* tile)
 {
     const uint32_t hdr_err = check_header(s, g, RANK);
     if (hdr_err) {
@@ -242,6 +247,32 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 #pragma unroll
                     for (int r = 0; r < 4; r++)
                         if (r < ey) store_run_masked<8>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, ex);
+                } else if (VEC4) {
+                    // the plane goes through LDS so that every store instruction
+                    // writes 4 whole rows of 64 values (a lane's own 4x8 patch
+                    // would give each instruction half-filled 32-byte pieces)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        float* t = tile + (4 * py + r) * kTilePitch + 8 * px;
+                        *reinterpret_cast<float4*>(t) = make_float4((float)d[8 * r] * ebx2, (float)d[8 * r + 1] * ebx2,
+                                                                    (float)d[8 * r + 2] * ebx2, (float)d[8 * r + 3] * ebx2);
+                        *reinterpret_cast<float4*>(t + 4) = make_float4((float)d[8 * r + 4] * ebx2, (float)d[8 * r + 5] * ebx2,
+                                                                        (float)d[8 * r + 6] * ebx2, (float)d[8 * r + 7] * ebx2);
+                    }
+                    __syncthreads();  // one wave: orders the tile's writes before its reads
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        y + (z * g.n[1] + org[1]) * g.n[2] + org[2], (short)0, -1, kBufferFlags);
+                    // offsets stay below 2^32: 32 rows of a contiguous extent below 2^25
+                    const uint32_t voff = 4u * ((uint32_t)(lane >> 4) * (uint32_t)g.n[2] + 4u * (lane & 15));
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        const float4 v = *reinterpret_cast<const float4*>(tile + (4 * i + (lane >> 4)) * kTilePitch +
+                                                                          4 * (lane & 15));
+                        const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                            __float_as_uint(v.w)};
+                        __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2], 0);
+                    }
+                    __syncthreads();  // the tile is rewritten by the next step
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; r++) store_run<8, VEC4>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2);
