@@ -62,21 +62,23 @@ __device__ __forceinline__ void log_escapes(const int (&d)[32], uint32_t (&P)[16
 template <bool ESC>
 __device__ __forceinline__ bool finish_step(const int (&d)[32], uint32_t (&P)[16], EscapeLog& log, uint32_t n0, int lane)
 {
-    uint32_t eacc = 0;
-    pack_codes(d, P, eacc);
-    const bool esc = __ballot(eacc > kEscapeLimit) != 0;
+    int dmin = 0, dmax = 0;
+    pack_codes(d, P, dmin, dmax);
+    const bool esc = __ballot(dmax > kMaxCodeDelta || dmin < -kMaxCodeDelta) != 0;
     if (ESC && esc) log_escapes(d, P, log, n0, lane);
     transpose16(P);
     return esc;
 }
 
-// prequantize 32 values; `facc` tracks max |p| (as shifted bits)
-__device__ __forceinline__ void prequant32(const float (&v)[32], float inv, uint32_t& facc, int (&q)[32])
+// prequantize 32 values; `facc` tracks max |p| with NaN propagating
+// (v_maximum3_f32), so one compare per step (!(facc < 2^31)) finds NaN, Inf
+// or an overflowing product
+__device__ __forceinline__ void prequant32(const float (&v)[32], float inv, float& facc, int (&q)[32])
 {
 #pragma unroll
     for (int i = 0; i < 32; i += 2) {
         const float p0 = v[i] * inv, p1 = v[i + 1] * inv;
-        facc = max(facc, max(__float_as_uint(p0) << 1, __float_as_uint(p1) << 1));
+        facc = __builtin_elementwise_maximum(facc, __builtin_elementwise_maximum(__builtin_fabsf(p0), __builtin_fabsf(p1)));
         q[i] = (int)__builtin_rintf(p0);
         q[i + 1] = (int)__builtin_rintf(p1);
     }
@@ -220,7 +222,7 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
 template <int RANK, bool EDGE, bool VEC4, bool ESC>
 __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
                                       int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
-                                      uint32_t& facc, EscapeLog& log)
+                                      float& facc, EscapeLog& log)
 {
     // the logging pass (ESC) keeps one copy of the step code: it runs rarely
     // and must not add to the register budget of the fast pass
@@ -391,11 +393,12 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
     const Lane l = lane_geo<RANK>(g, c, lane);
     float h[32], v[32];
     prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
-    uint32_t nz[16], facc = 0;
+    uint32_t nz[16];
+    float facc = 0.0f;
     EscapeLog log{oidx, oval, 0};
     if (l.edge) layer<RANK, true, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     else layer<RANK, false, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    return ((uint64_t)(uint32_t)log.count << 32) | facc;
+    return ((uint64_t)(uint32_t)log.count << 32) | __float_as_uint(facc);
 }
 
 // Rare path: a step saw NaN/Inf or |x*inv| >= 2^31.  Re-read the layer's
@@ -447,7 +450,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
                                            float (&v)[32], CompressLds& S, uint64_t (&F)[16])
 {
     uint32_t nz[16];
-    uint32_t facc = 0;
+    float facc = 0.0f;
     uint32_t* Wl = S.w[wave];
     EscapeLog log{S.oidx[wave], S.oval[wave], 0};
     if (wave < l.L) {
@@ -456,7 +459,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
         if (slow) {  // edge chunk, or escapes to log
             const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
             log.count = (int)(r >> 32);
-            facc = max(facc, (uint32_t)r);
+            facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
 #pragma unroll
             for (int b = 0; b < 16; b++)
                 nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
@@ -467,7 +470,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
         for (int b = 0; b < 16; b++) nz[b] = 0u;
     }
     uint32_t err = 0;
-    if (__ballot(facc >= kPrequantLimit)) {
+    if (__ballot(!(facc < 2147483648.0f))) {  // NaN, Inf or |x*inv| >= 2^31 somewhere in the layer
         err = classify_errors(x, out, g.scratch_off, c, wave, inv, lane);
 #pragma unroll
         for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);

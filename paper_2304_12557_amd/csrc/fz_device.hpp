@@ -58,7 +58,6 @@ __device__ __forceinline__ int prequant(float v, float inv, uint32_t& acc)
     acc = max(acc, __float_as_uint(p) << 1);
     return (int)__builtin_rintf(p);
 }
-constexpr uint32_t kPrequantLimit = 0x4F000000u << 1;  // bits(2^31) << 1
 
 __device__ __forceinline__ uint32_t absu(int d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
 
@@ -66,10 +65,11 @@ typedef short fz_short2 __attribute__((ext_vector_type(2)));
 
 // Sign-magnitude 16-bit codes of d[i] and d[i+16] packed into one word
 // (Sec. 3.2: sign in the MSB, magnitude below), computed on the packed low
-// halves with 16-bit lane arithmetic.  `eacc` collects d + 32767 as unsigned
-// so that one compare per step (> 65534) finds deltas outside [-32767, 32767],
-// whose codes the escape path then replaces.
-__device__ __forceinline__ void pack_codes(const int (&d)[32], uint32_t (&P)[16], uint32_t& eacc)
+// halves with 16-bit lane arithmetic.  `dmin` / `dmax` collect the range of
+// the deltas (one v_min3 / v_max3 per pair) so that one compare per step
+// finds deltas outside [-32767, 32767], whose codes the escape path then
+// replaces.
+__device__ __forceinline__ void pack_codes(const int (&d)[32], uint32_t (&P)[16], int& dmin, int& dmax)
 {
 #pragma unroll
     for (int i = 0; i < 16; i++) {
@@ -77,10 +77,12 @@ __device__ __forceinline__ void pack_codes(const int (&d)[32], uint32_t (&P)[16]
         const fz_short2 xs = __builtin_bit_cast(fz_short2, x);
         const fz_short2 mag = __builtin_elementwise_max(xs, (fz_short2)0 - xs);
         P[i] = __builtin_bit_cast(uint32_t, mag) | (x & 0x80008000u);
-        eacc = max(eacc, max((uint32_t)d[i] + 32767u, (uint32_t)d[i + 16] + 32767u));
+        dmax = max(dmax, max(d[i], d[i + 16]));
+        dmin = min(dmin, min(d[i], d[i + 16]));
     }
 }
-constexpr uint32_t kEscapeLimit = 65534u;
+constexpr uint32_t kEscapeLimit = 65534u;  // d + 32767 above this (as unsigned): an escape
+constexpr int kMaxCodeDelta = 32767;
 
 // In-register bit transpose: on entry P[i] holds code i (low half) and code
 // i+16 (high half); on exit P[b] bit m = bit b of code m (Sec. 3.3's
@@ -94,10 +96,19 @@ __device__ __forceinline__ void tswap(uint32_t& a, uint32_t& b)
     b = nb;
 }
 
+// the byte stage of the transpose: two byte permutes per pair of words
+__device__ __forceinline__ void tswap8(uint32_t& a, uint32_t& b)
+{
+    const uint32_t na = __builtin_amdgcn_perm(b, a, 0x06020400u);  // a0 b0 a2 b2
+    const uint32_t nb = __builtin_amdgcn_perm(b, a, 0x07030501u);  // a1 b1 a3 b3
+    a = na;
+    b = nb;
+}
+
 __device__ __forceinline__ void transpose16(uint32_t (&P)[16])
 {
 #pragma unroll
-    for (int i = 0; i < 8; i++) tswap<8, 0x00FF00FFu>(P[i], P[i + 8]);
+    for (int i = 0; i < 8; i++) tswap8(P[i], P[i + 8]);
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const int i = (j & 3) | ((j & 4) << 1);
