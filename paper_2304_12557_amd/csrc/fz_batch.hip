@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         const bool skip = reinterpret_cast<const Scratch*>(J.out + g.scratch_off)->pre_status != 0;
         const float inv = *reinterpret_cast<const float*>(J.out + kOffInv);
         const Lane l = lane_geo<RANK>(g, c, lane);
-        if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v);
+        if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         uint64_t F[16];
         int nout = 0;
         if (!skip) nout = chunk_layer<RANK, VEC4>(J.x, J.out, g, c, l, wave, lane, inv, h, v, S, F);
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         if (jn == j && !skip) {  // same field: start the next chunk's loads now
             const Lane ln = lane_geo<RANK>(g, tn - J.chunk0, lane);
             if (!ln.edge) {
-                prefetch<RANK, VEC4>(J.x, g, ln, wave, lane, h, v);
+                prefetch<RANK, VEC4>(J.x, g, ln, wave, lane, h, v, swept_down<RANK>(wave));
                 loaded = true;
             }
         }

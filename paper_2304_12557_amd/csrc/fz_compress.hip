@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     if (c >= g.n_chunks) return;
     float h[32], v[32];
     Lane l = lane_geo<RANK>(g, c, lane);
-    if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
+    if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
 
     for (;;) {
         uint64_t F[16];
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
         if (cn < g.n_chunks) {  // start loading the next chunk while this one is placed
             l = lane_geo<RANK>(g, cn, lane);
-            if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v);
+            if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         }
         chunk_place(out, g, c, wave, lane, F, nout, S);
         if (cn >= g.n_chunks) break;

@@ -212,6 +212,60 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
 }
 
 // ------------------------------------------------------------- one layer
+// In-plane part of the Lorenzo difference, after the difference along the
+// sweep dimension.  3-D: `a` is a plane difference; Dy then Dx give d.
+template <bool EDGE>
+__device__ __forceinline__ void inplane3(const int (&a)[32], int (&d)[32], const Lane& l, int lane)
+{
+    const int py = lane & 7, px = lane >> 3;
+    int b[32];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {  // Dy; row 0 takes row 3 of lane-1 (0 for py == 0)
+        const int up = shift_up1_raw(a[24 + c]);
+        b[c] = a[c] - (py == 0 ? 0 : up);
+    }
+#pragma unroll
+    for (int r = 1; r < 4; r++)
+#pragma unroll
+        for (int c = 0; c < 8; c++) b[8 * r + c] = a[8 * r + c] - a[8 * (r - 1) + c];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {  // Dx; column 0 takes column 7 of lane-8 (0 for px == 0)
+        const int left = lane_value(b[8 * r + 7], lane - 8);
+        d[8 * r] = b[8 * r] - (px == 0 ? 0 : left);
+#pragma unroll
+        for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
+    }
+    if (EDGE) {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 8; c++)
+                if (!(r < l.ev && c < l.eh)) d[8 * r + c] = 0;
+    }
+}
+
+// 2-D: `b` holds the two row differences of the step (rows 2s, 2s+1); Dx
+// gives d.
+template <bool EDGE>
+__device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const Lane& l, int lane, int s)
+{
+#pragma unroll
+    for (int r = 0; r < 2; r++) {  // Dx; column 0 takes column 15 of lane-1 (0 at lane 0)
+        const int left = shift_up1_raw(b[16 * r + 15]);
+        d[16 * r] = b[16 * r] - (lane == 0 ? 0 : left);
+#pragma unroll
+        for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
+    }
+    if (EDGE) {
+        const bool r1 = 2 * s + 1 < l.ext[0];
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            if (!(c < l.eh)) d[c] = 0;
+            if (!(c < l.eh && r1)) d[16 + c] = 0;
+        }
+    }
+}
+
 // `h` holds the halo (3-D: the plane before the layer; 2-D: the two rows
 // before it, of which the second is used; 1-D: unused) and `v` the first
 // step, both loaded ahead of time.  The plane-b word of step t goes to
@@ -229,7 +283,6 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
     bool esc = false;
 #pragma unroll
     for (int b = 0; b < 16; b++) nz[b] = 0u;
-    const int py = lane & 7, px = lane >> 3;
     // previous-step state: 3-D plane (32), 2-D row (16), 1-D last value (uniform)
     int qprev[32];
     int carry1 = 0;
@@ -281,30 +334,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
                 a[i] = q[i] - qprev[i];  // Dz
                 qprev[i] = q[i];
             }
-            int b[32];
-#pragma unroll
-            for (int c = 0; c < 8; c++) {  // Dy; row 0 takes row 3 of lane-1 (0 for py == 0)
-                const int up = shift_up1_raw(a[24 + c]);
-                b[c] = a[c] - (py == 0 ? 0 : up);
-            }
-#pragma unroll
-            for (int r = 1; r < 4; r++)
-#pragma unroll
-                for (int c = 0; c < 8; c++) b[8 * r + c] = a[8 * r + c] - a[8 * (r - 1) + c];
-#pragma unroll
-            for (int r = 0; r < 4; r++) {  // Dx; column 0 takes column 7 of lane-8 (0 for px == 0)
-                const int left = lane_value(b[8 * r + 7], lane - 8);
-                d[8 * r] = b[8 * r] - (px == 0 ? 0 : left);
-#pragma unroll
-                for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
-            }
-            if (EDGE) {
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-#pragma unroll
-                    for (int c = 0; c < 8; c++)
-                        if (!(r < l.ev && c < l.eh)) d[8 * r + c] = 0;
-            }
+            inplane3<EDGE>(a, d, l, lane);
         } else if (RANK == 2) {
             int b[32];
 #pragma unroll
@@ -313,21 +343,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
                 b[16 + c] = q[16 + c] - q[c];
                 qprev[c] = q[16 + c];
             }
-#pragma unroll
-            for (int r = 0; r < 2; r++) {  // Dx; column 0 takes column 15 of lane-1 (0 at lane 0)
-                const int left = shift_up1_raw(b[16 * r + 15]);
-                d[16 * r] = b[16 * r] - (lane == 0 ? 0 : left);
-#pragma unroll
-                for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
-            }
-            if (EDGE) {
-                const bool r1 = 2 * s + 1 < l.ext[0];
-#pragma unroll
-                for (int c = 0; c < 16; c++) {
-                    if (!(c < l.eh)) d[c] = 0;
-                    if (!(c < l.eh && r1)) d[16 + c] = 0;
-                }
-            }
+            inplane2<EDGE>(b, d, l, lane, s);
         } else {
             const int left = shift_up1_raw(q[31]);
             d[0] = q[0] - (lane == 0 ? carry1 : left);
@@ -357,11 +373,87 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
     return esc;
 }
 
-// Load the halo and the first step of layer k of a chunk ahead of time.
+// Layer k swept downwards (fast path of odd layers, 2-D and 3-D, chunks not
+// cut by the field's edge).  An odd layer's halo is the top plane of the
+// layer below it, and an even layer's halo the top plane of an odd layer; in
+// this order each halo plane is loaded in the same iteration as by the wave
+// that owns it, so the second load is served by the cache.  `h` holds the top
+// step of the layer and `v` the one below it.  The deltas and words are those
+// of the forward sweep; escapes are only detected (the out-of-line pass logs
+// them in code order).
+template <int RANK, bool VEC4>
+__device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
+                                          int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
+                                          float& facc, EscapeLog& log)
+{
+    static_assert(RANK >= 2, "the 1-D halo is one value");
+    bool esc = false;
+#pragma unroll
+    for (int b = 0; b < 16; b++) nz[b] = 0u;
+    int cq[32];  // q of the step being coded (3-D: its plane; 2-D: its two rows)
+    prequant32(h, inv, facc, cq);
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+        const int t = 3 - it, s = 4 * k + t;
+        float vn[32];
+        if (it < 3) load_step<RANK, false, VEC4>(x, g, l, s - 2, lane, vn);  // s - 2 = 4k - 1 at it = 2: the halo
+        __builtin_amdgcn_sched_barrier(0);
+        int ql[32];  // q of step s - 1
+        prequant32(v, inv, facc, ql);
+        int d[32];
+        if (RANK == 3) {
+            int a[32];
+#pragma unroll
+            for (int i = 0; i < 32; i++) {
+                a[i] = cq[i] - ql[i];  // Dz
+                cq[i] = ql[i];
+            }
+            inplane3<false>(a, d, l, lane);
+        } else {
+            int b[32];
+#pragma unroll
+            for (int c = 0; c < 16; c++) {  // Dy: row 2s against row 2s-1, row 2s+1 against row 2s
+                b[c] = cq[c] - ql[16 + c];
+                b[16 + c] = cq[16 + c] - cq[c];
+            }
+#pragma unroll
+            for (int i = 0; i < 32; i++) cq[i] = ql[i];
+            inplane2<false>(b, d, l, lane, s);
+        }
+        uint32_t P[16];
+        esc |= finish_step<false>(d, P, log, (uint32_t)s * kStepCodes, lane);
+#pragma unroll
+        for (int bb = 0; bb < 16; bb++) {
+            Wl[(bb * 4 + t) * 64 + lane] = P[bb];
+            nz[bb] |= P[bb];
+        }
+        if (it < 3) {
+#pragma unroll
+            for (int i = 0; i < 32; i++) v[i] = vn[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return esc;
+}
+
+// Whether layer k of a chunk not cut by the field's edge is swept downwards.
+template <int RANK>
+__device__ __forceinline__ bool swept_down(int k)
+{
+    return RANK >= 2 && (k & 1);
+}
+
+// Load the first two steps that layer k of a chunk uses ahead of time: the
+// halo and the first step (upwards), or the top two steps (downwards).
 template <int RANK, bool VEC4>
 __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom& g, const Lane& l, int k, int lane,
-                                         float (&h)[32], float (&v)[32])
+                                         float (&h)[32], float (&v)[32], bool down = false)
 {
+    if (down && k < l.L) {
+        load_step<RANK, false, VEC4>(x, g, l, 4 * k + 3, lane, h);
+        load_step<RANK, false, VEC4>(x, g, l, 4 * k + 2, lane, v);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 32; i++) {  // every path defines both, so no old value stays live
         h[i] = 0.0f;
@@ -436,39 +528,18 @@ struct CompressLds {
     uint64_t ticket;
     uint32_t oidx[kLayers][kLayerOutlierCap];
     int32_t oval[kLayers][kLayerOutlierCap];
-    uint32_t w[kLayers][kPlanes * 4 * 64];  // bricks of each wave's layer
+    // per wave: the bricks of its layer (as plane-step words)
+    uint32_t w[kLayers][kPlanes * 4 * 64];
 };
 
-// Wave `wave`'s layer of chunk c: bricks into S.w[wave], escapes into its
-// log, the layer's flags into the stream, its counts into S.  `h` / `v` hold
-// the prefetched halo and first step unless the chunk is cut by the field's
-// edge (the out-of-line pass then loads its own).  F receives the layer's
-// per-plane ballots; returns the layer's logged escape count.
-template <int RANK, bool VEC4>
-__device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
-                                           int64_t c, const Lane& l, int wave, int lane, float inv, float (&h)[32],
-                                           float (&v)[32], CompressLds& S, uint64_t (&F)[16])
+// Tail of a wave's layer: the data-dependent status bits (NaN/Inf or an
+// overflowing product, seen in facc; too many escapes), the flags of the
+// zero-block encoder (one ballot per bit plane, F) written to the stream, and
+// the layer's counts in S.  Returns the layer's escape count.
+__device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+                                           int64_t c, int wave, int lane, float inv, const uint32_t (&nz)[16],
+                                           float facc, const EscapeLog& log, CompressLds& S, uint64_t (&F)[16])
 {
-    uint32_t nz[16];
-    float facc = 0.0f;
-    uint32_t* Wl = S.w[wave];
-    EscapeLog log{S.oidx[wave], S.oval[wave], 0};
-    if (wave < l.L) {
-        bool slow = l.edge;
-        if (!slow) slow = layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
-        if (slow) {  // edge chunk, or escapes to log
-            const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
-            log.count = (int)(r >> 32);
-            facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
-#pragma unroll
-            for (int b = 0; b < 16; b++)
-                nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
-                        Wl[(b * 4 + 3) * 64 + lane];
-        }
-    } else {
-#pragma unroll
-        for (int b = 0; b < 16; b++) nz[b] = 0u;
-    }
     uint32_t err = 0;
     if (__ballot(!(facc < 2147483648.0f))) {  // NaN, Inf or |x*inv| >= 2^31 somewhere in the layer
         err = classify_errors(x, out, g.scratch_off, c, wave, inv, lane);
@@ -495,6 +566,47 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
         if (err) atomicOr(&S.err, err);
     }
     return nout;
+}
+
+// Wave `wave`'s layer of chunk c: bricks into S.w[wave], escapes into its
+// log, the layer's flags into the stream, its counts into S.  `h` / `v` hold
+// the prefetched halo and first step unless the chunk is cut by the field's
+// edge (the out-of-line pass then loads its own).  F receives the layer's
+// per-plane ballots; returns the layer's logged escape count.
+template <int RANK, bool VEC4>
+__device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+                                           int64_t c, const Lane& l, int wave, int lane, float inv, float (&h)[32],
+                                           float (&v)[32], CompressLds& S, uint64_t (&F)[16])
+{
+    uint32_t nz[16];
+    float facc = 0.0f;
+    uint32_t* Wl = S.w[wave];
+    EscapeLog log{S.oidx[wave], S.oval[wave], 0};
+    if (wave < l.L) {
+        bool slow = l.edge;
+        if (!slow) {
+            if constexpr (RANK >= 2) {
+                slow = swept_down<RANK>(wave)
+                           ? layer_rev<RANK, VEC4>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
+                           : layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+            } else {
+                slow = layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+            }
+        }
+        if (slow) {  // edge chunk, or escapes to log
+            const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
+            log.count = (int)(r >> 32);
+            facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
+#pragma unroll
+            for (int b = 0; b < 16; b++)
+                nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
+                        Wl[(b * 4 + 3) * 64 + lane];
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < 16; b++) nz[b] = 0u;
+    }
+    return layer_flags(x, out, g, c, wave, lane, inv, nz, facc, log, S, F);
 }
 
 // After a workgroup barrier that follows chunk_layer on all 4 waves: the
