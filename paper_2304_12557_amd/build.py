@@ -1,7 +1,10 @@
 """Builds libfzmi.so (HIP, gfx950) in-tree with hipcc.
 
 Flags: -O3, fp contraction off, fp32 denormals kept, packed-fp32 instructions
-disabled.  Usage: python -m paper_2304_12557_amd.build  (or build()).
+disabled, and the compiler's wave-level atomic aggregation off (it broadcasts
+an atomic's result right after issuing it, so the wave waits for the atomic
+there; the compression kernels take their next ticket early and use it a
+layer later).  Usage: python -m paper_2304_12557_amd.build  (or build()).
 """
 import os
 import subprocess
@@ -15,6 +18,7 @@ ARCH = os.environ.get("FZ_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off", "-fno-fast-math",
     "-fno-gpu-flush-denormals-to-zero", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function", "-I" + os.path.join(os.path.dirname(HERE), "include"),
 ]
 

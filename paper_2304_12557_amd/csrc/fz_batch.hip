@@ -93,10 +93,12 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         const float inv = *reinterpret_cast<const float*>(J.out + kOffInv);
         const Lane l = lane_geo<RANK>(g, c, lane);
         if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
-        uint64_t F[16];
+        uint32_t tk;  // the next ticket, taken early by thread 0 (its return has the layer to arrive)
+        if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+        uint64_t F[16], myflag = 0;
         int nout = 0;
-        if (!skip) nout = chunk_layer<RANK, VEC4>(J.x, J.out, g, c, l, wave, lane, inv, h, v, S, F);
-        if (threadIdx.x == 0) S.ticket = atomicAdd(ticket, 1u);
+        if (!skip) nout = chunk_layer<RANK, VEC4>(J.x, J.out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t tn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
         const int jn = tn < total ? __builtin_amdgcn_readfirstlane(chunk_job[tn]) : -1;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
                 loaded = true;
             }
         }
-        if (!skip) chunk_place(J.out, g, c, wave, lane, F, nout, S);
+        if (!skip) chunk_place(J.out, g, c, wave, lane, F, myflag, nout, S);
         if (tn >= total) break;
         t = tn;
         j = jn;

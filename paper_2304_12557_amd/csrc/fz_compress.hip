@@ -38,16 +38,20 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
 
     for (;;) {
-        uint64_t F[16];
-        const int nout = chunk_layer<RANK, VEC4>(x, out, g, c, l, wave, lane, inv, h, v, S, F);
-        if (threadIdx.x == 0) S.ticket = atomicAdd(&scr->ticket, 1u);  // next chunk
+        // the next chunk's ticket, taken now so that its return has the whole
+        // layer to arrive
+        uint32_t tk;  // thread 0 only: a value on the other lanes would need a copy that waits for the atomic
+        if (threadIdx.x == 0) tk = atomicAdd(&scr->ticket, 1u);
+        uint64_t F[16], myflag;
+        const int nout = chunk_layer<RANK, VEC4>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
         if (cn < g.n_chunks) {  // start loading the next chunk while this one is placed
             l = lane_geo<RANK>(g, cn, lane);
             if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         }
-        chunk_place(out, g, c, wave, lane, F, nout, S);
+        chunk_place(out, g, c, wave, lane, F, myflag, nout, S);
         if (cn >= g.n_chunks) break;
         c = cn;
         __syncthreads();  // the LDS counts and logs are reused by the next chunk

@@ -534,11 +534,13 @@ struct CompressLds {
 
 // Tail of a wave's layer: the data-dependent status bits (NaN/Inf or an
 // overflowing product, seen in facc; too many escapes), the flags of the
-// zero-block encoder (one ballot per bit plane, F) written to the stream, and
-// the layer's counts in S.  Returns the layer's escape count.
+// zero-block encoder (one ballot per bit plane, F; lane b < 16 gets F[b] in
+// `myflag`, which chunk_place stores), and the layer's counts in S.  Returns
+// the layer's escape count.
 __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
                                            int64_t c, int wave, int lane, float inv, const uint32_t (&nz)[16],
-                                           float facc, const EscapeLog& log, CompressLds& S, uint64_t (&F)[16])
+                                           float facc, const EscapeLog& log, CompressLds& S, uint64_t (&F)[16],
+                                           uint64_t& myflag)
 {
     uint32_t err = 0;
     if (__ballot(!(facc < 2147483648.0f))) {  // NaN, Inf or |x*inv| >= 2^31 somewhere in the layer
@@ -551,15 +553,13 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 
     // flags of the zero-block encoder: one ballot per bit plane
     uint32_t nnz = 0;
-    uint64_t myflag = 0;
+    myflag = 0;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
         F[b] = __ballot(nz[b] != 0u);
         nnz += __popcll(F[b]);
         myflag = lane == b ? F[b] : myflag;
     }
-    if (lane < 16)
-        reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
     if (lane == 0) {
         S.nnz[wave] = nnz;
         S.nout[wave] = (uint32_t)nout;
@@ -569,14 +569,14 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 }
 
 // Wave `wave`'s layer of chunk c: bricks into S.w[wave], escapes into its
-// log, the layer's flags into the stream, its counts into S.  `h` / `v` hold
-// the prefetched halo and first step unless the chunk is cut by the field's
-// edge (the out-of-line pass then loads its own).  F receives the layer's
-// per-plane ballots; returns the layer's logged escape count.
+// log, its counts into S.  `h` / `v` hold the prefetched halo and first step
+// unless the chunk is cut by the field's edge (the out-of-line pass then
+// loads its own).  F receives the layer's per-plane ballots and `myflag` the
+// flag word lane b < 16 stores; returns the layer's logged escape count.
 template <int RANK, bool VEC4>
 __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
                                            int64_t c, const Lane& l, int wave, int lane, float inv, float (&h)[32],
-                                           float (&v)[32], CompressLds& S, uint64_t (&F)[16])
+                                           float (&v)[32], CompressLds& S, uint64_t (&F)[16], uint64_t& myflag)
 {
     uint32_t nz[16];
     float facc = 0.0f;
@@ -606,17 +606,21 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
 #pragma unroll
         for (int b = 0; b < 16; b++) nz[b] = 0u;
     }
-    return layer_flags(x, out, g, c, wave, lane, inv, nz, facc, log, S, F);
+    return layer_flags(x, out, g, c, wave, lane, inv, nz, facc, log, S, F, myflag);
 }
 
 // After a workgroup barrier that follows chunk_layer on all 4 waves: the
-// chunk's size goes to its state word (the placement kernels turn the sizes
-// into offsets), its escape count to the table, the counts to the header,
-// and its payload is assembled in its staging slot: nonzero bricks in
-// (layer, plane, patch) order, then the escape pairs padded to 16 bytes.
+// layer's flags go to the stream (stored only here, so that no wait before
+// the barrier covers them), the chunk's size to its state word (the
+// placement kernels turn the sizes into offsets), its escape count to the
+// table, the counts to the header, and its payload is assembled in its
+// staging slot: nonzero bricks in (layer, plane, patch) order, then the
+// escape pairs padded to 16 bytes.
 __device__ __forceinline__ void chunk_place(uint8_t* __restrict__ out, const Geom& g, int64_t c, int wave, int lane,
-                                            const uint64_t (&F)[16], int nout, CompressLds& S)
+                                            const uint64_t (&F)[16], uint64_t myflag, int nout, CompressLds& S)
 {
+    if (lane < 16)
+        reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
     uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
     const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
     const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];
@@ -684,24 +688,32 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
                                              const Geom& g, int64_t blk, int64_t nblk)
 {
     __shared__ uint32_t s_red[3][4];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
-    auto take = [&](float e) {
-        const uint32_t key = float_key(e);
-        const bool fin = __builtin_isfinite(e);
-        bad |= fin ? 0u : 1u;
-        lo = fin ? min(lo, key) : lo;
-        hi = fin ? max(hi, key) : hi;
+    // NaN-propagating minimum / maximum over the raw values: the range is only
+    // used when every value is finite, and a NaN or an infinity shows up in
+    // the result (the minimum is -Inf or NaN, or the maximum +Inf or NaN)
+    float fmn = __builtin_inff(), fmx = -__builtin_inff();
+    auto take4 = [&](const float4& v) {
+        fmn = __builtin_elementwise_minimum(__builtin_elementwise_minimum(fmn, v.x), v.y);
+        fmx = __builtin_elementwise_maximum(__builtin_elementwise_maximum(fmx, v.x), v.y);
+        fmn = __builtin_elementwise_minimum(__builtin_elementwise_minimum(fmn, v.z), v.w);
+        fmx = __builtin_elementwise_maximum(__builtin_elementwise_maximum(fmx, v.z), v.w);
     };
     const int64_t stride = nblk * 256;
     const int64_t tid = blk * 256 + threadIdx.x;
     const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     const int64_t n4 = vec ? n / 4 : 0;
     const float4* x4 = reinterpret_cast<const float4*>(x);
-    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) {
-        const float4 v = x4[i];
-        take(v.x); take(v.y); take(v.z); take(v.w);
+    // backwards, so that the front of the field, which the compression
+    // kernel reads first, is the most recently read (one load per
+    // iteration: unrolling by strided loads measured slower)
+    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) take4(x4[i]);
+    for (int64_t k = 4 * n4 + tid; k < n; k += stride) {
+        fmn = __builtin_elementwise_minimum(fmn, x[k]);
+        fmx = __builtin_elementwise_maximum(fmx, x[k]);
     }
-    for (int64_t k = 4 * n4 + tid; k < n; k += stride) take(x[k]);
+    const bool some = fmn <= fmx;  // false for a thread without values (and for NaN)
+    uint32_t bad = (fmn >= -3.40282347e38f && fmx <= 3.40282347e38f) ? 0u : 1u;
+    uint32_t lo = some ? float_key(fmn) : 0xFFFFFFFFu, hi = some ? float_key(fmx) : 0u;
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, sh));

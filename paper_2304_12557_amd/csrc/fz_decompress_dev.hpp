@@ -4,7 +4,7 @@
 // The inverse of the compression pass (Sec. 4.3 calls the two pipelines
 // symmetric).  One wave per chunk sweeps its steps in order.  Per step each
 // lane loads word t of its nonzero bricks (their positions follow from the bit
-// flags by popcount and mbcnt, Sec. 3.4) while the previous step is computed;
+// flags by popcount and mbcnt, Sec. 3.4) two steps before it computes them;
 // it undoes the bitshuffle with the same in-register transpose, decodes the
 // sign-magnitude codes (Sec. 3.2), and inverts the Lorenzo predictor as
 // inclusive prefix sums: along the patch in registers, across lanes for the
@@ -149,10 +149,10 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     constexpr uint32_t kZeroBrick = 0x80000000u;
     uint32_t voff[16];
     uint32_t cur = 0;
-    auto layer_offsets = [&](int k) {
+    auto layer_offsets = [&](int k) {  // past the last layer: all bricks zero
 #pragma unroll
         for (int b = 0; b < 16; b++) {
-            const uint64_t f = F[k * kPlanes + b];
+            const uint64_t f = k < L ? F[k * kPlanes + b] : 0ull;
             voff[b] = ((f >> lane) & 1ull) ? 16u * (cur + mbcnt(f)) : kZeroBrick;
             cur += (uint32_t)__popcll(f);
         }
@@ -172,27 +172,29 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 #pragma unroll
     for (int i = 0; i < 16; i++) carry2[i] = 0;
 
-    uint32_t Wc[16];
-    layer_offsets(0);
-    load_words(0, Wc);
-    for (int k = 0; k < L; k++) {
+    // The words of a step are loaded two steps ahead: the wait for them then
+    // leaves the previous step's stores outstanding (the counter of
+    // outstanding vector memory operations covers stores too, in issue order).
+    // W[t] holds the words of step t of a layer.  Every load is issued
+    // unconditionally, so no register that a load is still filling is ever
+    // copied at a join: iteration k = -1 loads zero bricks at t = 0, 1 and
+    // layer 0's first words at t = 2, 3; the last layer loads the zero
+    // bricks of the layer after it.
+    uint32_t W[4][16];
+#pragma unroll
+    for (int b = 0; b < 16; b++) voff[b] = kZeroBrick;
+    for (int k = -1; k < L; k++) {
 #pragma unroll
         for (int t = 0; t < 4; t++) {
+            if (t == 2) layer_offsets(k + 1);  // the last load of layer k was issued at t = 1
+            load_words(t < 2 ? t + 2 : t - 2, W[(t + 2) & 3]);
+            __builtin_amdgcn_sched_barrier(0);
             const int st = 4 * k + t;
             const int64_t step_lo = RANK == 3 ? st : RANK == 2 ? 2 * st : (int64_t)kStepCodes * st;
-            if (step_lo >= ext[0]) break;
-            // the next step's words are loaded while this step is computed
-            uint32_t Wn[16];
-            if (t < 3) {
-                load_words(t + 1, Wn);
-            } else if (k + 1 < L) {
-                layer_offsets(k + 1);
-                load_words(0, Wn);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            if (k < 0 || step_lo >= ext[0]) continue;
             uint32_t P[16];
 #pragma unroll
-            for (int b = 0; b < 16; b++) P[b] = Wc[b];
+            for (int b = 0; b < 16; b++) P[b] = W[t][b];
             transpose16(P);
             int d[32];
             decode_codes(P, d);
@@ -218,6 +220,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += ex_;
                 }
                 // prefix along y inside the patch, carry across lanes -1, -2, -4
+                // (within a group of 8 lanes: a shift inside the 16-lane row)
 #pragma unroll
                 for (int r = 1; r < 4; r++)
 #pragma unroll
@@ -226,11 +229,12 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                 for (int cc = 0; cc < 8; cc++) {
                     const int C = d[24 + cc];
                     int inc = C;
-#pragma unroll
-                    for (int sh = 1; sh < 8; sh <<= 1) {
-                        const int tv = lane_value(inc, lane - sh);
-                        inc += py >= sh ? tv : 0;
-                    }
+                    int tv = row_shr<1>(inc);
+                    inc += py >= 1 ? tv : 0;
+                    tv = row_shr<2>(inc);
+                    inc += py >= 2 ? tv : 0;
+                    tv = row_shr<4>(inc);
+                    inc += py >= 4 ? tv : 0;
                     const int ex_ = inc - C;
 #pragma unroll
                     for (int r = 0; r < 4; r++) d[8 * r + cc] += ex_;
@@ -320,8 +324,6 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     store_run<32, VEC4>(y + x0, d, ebx2);
                 }
             }
-#pragma unroll
-            for (int b = 0; b < 16; b++) Wc[b] = Wn[b];
             __builtin_amdgcn_sched_barrier(0);
         }
     }

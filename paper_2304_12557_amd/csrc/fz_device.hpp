@@ -27,6 +27,15 @@ __device__ __forceinline__ int shift_up1(int v, int lane)
     return lane == 0 ? 0 : r;
 }
 
+// value of `v` held by lane - SH within the same row of 16 lanes (0 for the
+// first SH lanes of a row)
+template <int SH>
+__device__ __forceinline__ int row_shr(int v)
+{
+    static_assert(SH >= 1 && SH <= 15, "row shift");
+    return __builtin_amdgcn_update_dpp(0, v, 0x110 + SH, 0xf, 0xf, true);
+}
+
 // value of `v` held by lane `src` (any lane; indices wrap modulo 64)
 __device__ __forceinline__ int lane_value(int v, int src)
 {

@@ -115,6 +115,31 @@ def test_status_bits_match_oracle():
     assert fz.stream_info(buf)["status"] == st == O.ERR_OUTLIER_CAP
 
 
+@pytest.mark.parametrize("where", ["first", "last", "tail", "middle"])
+@pytest.mark.parametrize("val", [np.inf, -np.inf, np.nan])
+def test_rel_range_nonfinite(where, val):
+    """A NaN or an infinity anywhere (also among the last values that do not
+    fill a 16-byte vector) fails the REL range pass, as in the oracle (the
+    rest of a failed stream is unspecified)."""
+    x = synth.sine_field((100003,), seed=11)  # n % 4 == 3: a scalar tail
+    i = {"first": 0, "last": x.size - 1, "tail": x.size - 2, "middle": 51234}[where]
+    x[i] = val
+    print("nonfinite", where, val, flush=True)
+    _, st = O.compress(x, 1e-3, O.EB_REL)
+    buf, s = gpu_compress(x, 1e-3, O.EB_REL)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_NONFINITE
+
+
+def test_rel_range_signed_zero_and_constant():
+    """The range pass on signed zeros and constant fields gives the oracle's
+    header (vmin / vmax, eb) and stream."""
+    x = synth.sine_field((20, 40, 70), seed=12)
+    x[x < 0] = np.float32(-0.0)  # minimum -0.0, all others >= 0
+    check_case(x, 1e-3)
+    check_case(np.full((33, 1030), -0.0, dtype=np.float32), 1e-3)
+    check_case(np.full((70001,), -2.5, dtype=np.float32), 1e-3)
+
+
 def test_decompress_rejects_bad_stream():
     x = synth.sine_field((20, 40, 70), seed=5)
     buf, s = gpu_compress(x, 1e-3, O.EB_REL)
