@@ -201,21 +201,14 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             if (nout) esc_bad |= apply_escapes(P, d, pairs, nout, seen, (uint32_t)st * kStepCodes, lane);
 
             if (RANK == 3) {
-                // prefix along x inside the patch, carry across lanes lane-8, -16, -32
+                // prefix along x inside the patch, carry across the lanes 8 apart (DPP and lane swaps)
 #pragma unroll
                 for (int r = 0; r < 4; r++)
 #pragma unroll
                     for (int cc = 1; cc < 8; cc++) d[8 * r + cc] += d[8 * r + cc - 1];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int T = d[8 * r + 7];
-                    int inc = T;
-#pragma unroll
-                    for (int sh = 8; sh < 64; sh <<= 1) {
-                        const int tv = lane_value(inc, lane - sh);
-                        inc += lane >= sh ? tv : 0;
-                    }
-                    const int ex_ = inc - T;
+                    const int ex_ = excl_scan_stride8(d[8 * r + 7], lane);
 #pragma unroll
                     for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += ex_;
                 }

@@ -36,6 +36,32 @@ __device__ __forceinline__ int row_shr(int v)
     return __builtin_amdgcn_update_dpp(0, v, 0x110 + SH, 0xf, 0xf, true);
 }
 
+// value of `v` held by lane (i + 8) mod 16 of the same 16-lane row
+__device__ __forceinline__ int row_ror8(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);
+}
+
+// Exclusive prefix sum of `v` over the 8 lanes with the same lane & 7, in
+// the order of lane >> 3 (lanes 8 apart).  Within a 16-lane row the two
+// halves are paired by DPP; the rows' totals are combined with the lane
+// swaps (with both operands x, permlane16_swap gives the rows (x0, x0, x2,
+// x2) and (x1, x1, x3, x3), permlane32_swap gives (x0, x1, x0, x1)).
+__device__ __forceinline__ int excl_scan_stride8(int v, int lane)
+{
+    const int s1 = v + row_shr<8>(v);                   // upper half: its pair's inclusive sum
+    const int r8 = row_ror8(s1);                         // on every lane: a lane shift under a branch
+    const int u = (lane & 8) ? s1 : r8;                  // would read inactive lanes; the row's total
+    const auto p = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+    const int a = (int)p[0];                             // rows: R0, R0, R2, R2
+    const int c = a + (int)p[1];                         // rows: R0+R1, R0+R1, R2+R3, R2+R3
+    const auto q = __builtin_amdgcn_permlane32_swap((uint32_t)c, (uint32_t)c, false, false);
+    const int row = lane >> 4;
+    int o = (row & 1) ? a : 0;                           // rows 1, 3: R0, R2
+    o += (row & 2) ? (int)q[0] : 0;                      // rows 2, 3: + R0+R1
+    return o + s1 - v;
+}
+
 // value of `v` held by lane `src` (any lane; indices wrap modulo 64)
 __device__ __forceinline__ int lane_value(int v, int src)
 {
