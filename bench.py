@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU time of the oracle baseline")
     p.add_argument("--no-layers", action="store_true", help="skip the batched and serving measurements")
+    p.add_argument("--no-quality", action="store_true",
+                   help="skip the rate-distortion sweep and the overall-throughput measurement")
     p.add_argument("--batch-fields", type=int, default=256)
     p.add_argument("--serve-requests", type=int, default=2000, help="requests per offered-load level")
     p.add_argument("--serve-seconds", type=float, default=4.0, help="longest trace per offered-load level")
@@ -361,6 +363,79 @@ def bench_serving(n_requests, max_seconds, n_pool=48, seed=4000):
         "batched_capacity_GBps": round(capacity / 1e9, 1), "levels": levels,
     }
 
+# the paper's five value-range-relative bounds (Sec. 4.1) and its host-link
+# figures for the overall throughput (Sec. 4.6: PCIe 4.0 x16, and the per-GPU
+# share when 4 GPUs move data at once)
+REL_EBS = (1e-2, 5e-3, 1e-3, 5e-4, 1e-4)
+PAPER_LINKS_GBPS = (32.0, 11.4)
+
+
+def rate_distortion(xt, shape):
+    """Ratio, bitrate (32 / ratio) and distortion (the library's quality
+    pass) of the field at each of the paper's relative bounds."""
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    buf = torch.empty(fz.compress_bound(shape), dtype=torch.uint8, device=xt.device)
+    y = torch.empty_like(xt)
+    rows = []
+    for eb in REL_EBS:
+        fz.compress(xt, eb, "rel", out=buf)
+        fz.decompress(buf, shape, out=y)
+        info = fz.stream_info(buf)
+        assert info["status"] == 0
+        q = fz.quality(xt, y)
+        ratio = 4 * xt.numel() / int(info["total_bytes"])
+        eb_abs = eb * (float(info["vmax"]) - float(info["vmin"]))
+        rows.append({"eb": eb, "ratio": round(ratio, 3), "bitrate": round(32.0 / ratio, 4),
+                     "psnr_db": round(q["psnr"], 3), "max_abs_err": q["max_abs_err"],
+                     "max_err_over_eb": round(q["max_abs_err"] / eb_abs, 6)})
+    return rows
+
+
+def overall_throughput(xt, shape, eb, s_bytes, t_compr_gbps, steps):
+    """Overall data-transfer throughput (Sec. 4.6): compress on the device,
+    then move the stream to pinned host memory.  Reports the measured
+    device-to-host bandwidth, the paper's model ((BW * CR)^-1 + T^-1)^-1 at
+    that bandwidth and at the paper's link figures, and the same pipeline
+    timed directly (compress, then copy, back to back on one stream)."""
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    in_bytes = 4 * xt.numel()
+    ratio = in_bytes / s_bytes
+    host = torch.empty(s_bytes, dtype=torch.uint8, pin_memory=True)
+    buf = torch.empty(fz.compress_bound(shape), dtype=torch.uint8, device=xt.device)
+    fz.compress(xt, eb, "rel", out=buf)
+    src = buf[:s_bytes]
+    for _ in range(2):
+        host.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        host.copy_(src, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = s_bytes * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(steps):
+        fz.compress(xt, eb, "rel", out=buf)
+        host.copy_(src, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    measured = in_bytes * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    def model(link):
+        return 1.0 / (1.0 / (link * ratio) + 1.0 / t_compr_gbps)
+
+    return {"unit": "GB/s of input", "ratio": round(ratio, 3), "compress_GBps": round(t_compr_gbps, 2),
+            "d2h_GBps": round(bw, 2), "model_GBps": round(model(bw), 2), "measured_GBps": round(measured, 2),
+            "paper_links": [{"link_GBps": L, "model_GBps": round(model(L), 2)} for L in PAPER_LINKS_GBPS]}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -458,6 +533,10 @@ def main():
                      "traffic": measured_traffic(name, shape, a.eb),
                      "algorithmic_bytes": int(alg), "avg_launch_ms": round(t_ms, 4)},
     }
+    if not a.no_quality:
+        out["rate_distortion"] = rate_distortion(xt, shape)
+        out["overall_throughput"] = overall_throughput(xt, shape, a.eb, s_bytes, in_bytes / 1e9 / (tc * 1e-3),
+                                                       a.steps)
     if not a.no_layers:
         del buf, y
         torch.cuda.empty_cache()

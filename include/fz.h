@@ -115,7 +115,7 @@ size_t fz_header_bytes(const fz_dims *dims);
  * unspecified.  Returns FZ_OK once the work is enqueued. */
 int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
 
-/* fz_decompress -- the inverse pipeline (Sec. 4.3 describes it as symmetric
+/* fz_decompress -- the inverse pipeline (Sec. 4.4 describes it as symmetric
  * to compression).
  *   d_stream : device pointer to a stream made by fz_compress
  *   d_out    : N fp32 values (device, written)
@@ -230,6 +230,42 @@ int fz_server_stats(fz_server *s, fz_server_report *out);
 int fz_server_reset_stats(fz_server *s);
 /* Finishes every queued request, then frees the server. */
 int fz_server_destroy(fz_server *s);
+
+/* ------------------------------------------------------------ quality
+ * Distortion of a reconstruction y against its original x, the second of the
+ * evaluation metrics of Sec. 4.2 (PSNR over the value range; the paper's
+ * bitrate is 32 / compression ratio and needs no device work).  Each
+ * difference is taken in double, (double)x - (double)y, rounded once.
+ * Results, written to device memory at d_res:
+ *   max_abs_err : max |x - y|
+ *   mse         : (sum of (x - y)^2) / n, the sum in double
+ *   psnr        : 20 log10(vmax - vmin) - 10 log10(mse) dB; +inf when
+ *                 mse == 0, -inf when vmax == vmin and mse > 0
+ *   vmin, vmax  : the value range of x
+ *   n           : values compared
+ *   nonfinite   : positions where x or y is NaN or infinite; when > 0 every
+ *                 double field is NaN
+ * The sum's rounding order is fixed by n alone, so repeated calls give
+ * identical bits. */
+typedef struct {
+    double max_abs_err;
+    double mse;
+    double psnr;
+    double vmin, vmax;
+    uint64_t n;
+    uint64_t nonfinite;
+} fz_quality_report;
+
+/* Device scratch fz_quality needs (per-block partial results): at most
+ * 64 KiB.  0 on invalid dims. */
+size_t fz_quality_work_bytes(const fz_dims *dims);
+
+/* fz_quality -- d_x, d_y: N fp32 values each (device, read only); d_res:
+ * one fz_quality_report (device, written); d_work: fz_quality_work_bytes(dims)
+ * bytes (device).  Same dims limits as fz_compress.  Returns FZ_OK once the
+ * work is enqueued. */
+int fz_quality(const float *d_x, const float *d_y, const fz_dims *dims, fz_quality_report *d_res, void *d_work,
+               void *stream);
 
 /* Parse a host copy of the first n >= 128 bytes of a stream. */
 int fz_stream_info(const void *h_header, size_t n, fz_info *out);

@@ -21,7 +21,7 @@
  *   - zero-block encoder (bit flag per data block, prefix sum of block counts
  *     for offsets, copy of the nonzero blocks): Sec. 3.4;
  *   - value-range-relative error bound: Sec. 4.1 ("Baselines");
- *   - decompression is the symmetric inverse: Sec. 4.3.
+ *   - decompression is the symmetric inverse: Sec. 4.4.
  * The paper leaves the chunk shape, the order of codes inside a tile, the
  * handling of codes that do not fit in 16 bits, and the stream layout open;
  * this file follows the readings fixed in the stream format v1 (see the

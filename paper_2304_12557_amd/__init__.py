@@ -64,6 +64,12 @@ class FzServerReport(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double)]
 
 
+class FzQuality(ctypes.Structure):
+    _fields_ = [("max_abs_err", ctypes.c_double), ("mse", ctypes.c_double), ("psnr", ctypes.c_double),
+                ("vmin", ctypes.c_double), ("vmax", ctypes.c_double), ("n", ctypes.c_uint64),
+                ("nonfinite", ctypes.c_uint64)]
+
+
 class FzError(RuntimeError):
     def __init__(self, code, what=""):
         super().__init__("%s: %s (%d)" % (what, ERRORS.get(code, "unknown"), code))
@@ -114,6 +120,10 @@ def lib():
         for name in ("fz_server_reset_stats", "fz_server_destroy"):
             getattr(L, name).argtypes = [vp]
             getattr(L, name).restype = ctypes.c_int
+        L.fz_quality_work_bytes.argtypes = [dp]
+        L.fz_quality_work_bytes.restype = ctypes.c_size_t
+        L.fz_quality.argtypes = [vp, vp, dp, vp, vp, vp]
+        L.fz_quality.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -121,7 +131,7 @@ def lib():
 SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
-           "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy"]
+           "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality"]
 FZ_REQ_COMPRESS = 0
 FZ_REQ_DECOMPRESS = 1
 
@@ -196,6 +206,31 @@ def decompress(s, shape, out=None, err=None, stream=None):
     if rc:
         raise FzError(rc, "fz_decompress")
     return out
+
+
+def quality(x, y, stream=None):
+    """Distortion of y against x (float32 CUDA tensors of one shape, rank 1-3)
+    computed by the library's kernels; returns a dict with max_abs_err, mse,
+    psnr (dB), vmin, vmax, n, nonfinite.  Synchronizes the stream."""
+    import torch
+
+    for name, t in (("x", x), ("y", y)):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+    if tuple(x.shape) != tuple(y.shape):
+        raise ValueError("x and y differ in shape")
+    dims = dims_of(x.shape)
+    nwork = int(lib().fz_quality_work_bytes(ctypes.byref(dims)))
+    if nwork == 0:
+        raise FzError(1, "fz_quality_work_bytes")
+    work = torch.empty(nwork, dtype=torch.uint8, device=x.device)
+    res = torch.empty(ctypes.sizeof(FzQuality), dtype=torch.uint8, device=x.device)
+    rc = lib().fz_quality(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), ctypes.byref(dims),
+                          ctypes.c_void_p(res.data_ptr()), ctypes.c_void_p(work.data_ptr()), _stream_ptr(stream))
+    if rc:
+        raise FzError(rc, "fz_quality")
+    q = FzQuality.from_buffer_copy(bytes(res.cpu().numpy().tobytes()))
+    return {f: getattr(q, f) for f, _ in FzQuality._fields_}
 
 
 def stream_info(header):

@@ -1,7 +1,7 @@
 // fz_decompress_dev.hpp -- device code of the decompressor, shared by the
 // per-field kernel (fz_decompress.hip) and the batched one (fz_batch.hip).
 //
-// The inverse of the compression pass (Sec. 4.3 calls the two pipelines
+// The inverse of the compression pass (Sec. 4.4 calls the two pipelines
 // symmetric).  One wave per chunk sweeps its steps in order.  Per step each
 // lane loads word t of its nonzero bricks (their positions follow from the bit
 // flags by popcount and mbcnt, Sec. 3.4) two steps before it computes them;

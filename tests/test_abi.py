@@ -126,3 +126,23 @@ def test_server_argument_errors():
     assert L.fz_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == 1
     assert L.fz_server_wait(None, 1, None) == 1
     assert L.fz_server_destroy(None) == 1
+
+
+def test_quality_argument_errors():
+    L = fz.lib()
+    d = fz.dims_of((1000, 3))
+    p = ctypes.c_void_p(256)
+    work = L.fz_quality_work_bytes(ctypes.byref(d))
+    assert 32 <= work <= 64 * 1024 and work % 32 == 0
+    assert L.fz_quality_work_bytes(ctypes.byref(fz.dims_of((512, 512, 512)))) == 2048 * 32
+    assert L.fz_quality(None, p, ctypes.byref(d), p, p, None) == 1
+    assert L.fz_quality(p, None, ctypes.byref(d), p, p, None) == 1
+    assert L.fz_quality(p, p, ctypes.byref(d), None, p, None) == 1
+    assert L.fz_quality(p, p, ctypes.byref(d), p, None, None) == 1
+    assert L.fz_quality(p, p, None, p, p, None) == 1
+    bad = fz.FzDims()
+    bad.rank = 2
+    bad.n[0], bad.n[1] = 4, 0
+    assert L.fz_quality_work_bytes(ctypes.byref(bad)) == 0
+    assert L.fz_quality(p, p, ctypes.byref(bad), p, p, None) == 1
+    assert ctypes.sizeof(fz.FzQuality) == 56

@@ -26,6 +26,7 @@ import torch
 
 import paper_2304_12557_amd as fz
 from oracle import oracle as O
+from oracle import quality as Q
 import stream_np
 import synth
 
@@ -129,3 +130,23 @@ def test_cosmology_512(cosmo, eb):
         assert rtab[1] == table[c, 1], c
         start = payload_off + 16 * int(table[c, 0])
         assert np.array_equal(ref[656:], s[start:start + ref.size - 656]), c
+
+
+def test_cosmology_512_quality(cosmo):
+    """The distortion pass at full size on the round trip of the benchmark's
+    configuration (REL 1e-3): exact maximum and range, MSE within 1e-9 of the
+    oracle's float64 sum over 134M values."""
+    x = cosmo
+    print("case quality lognormal 512^3", flush=True)
+    xt = torch.from_numpy(x).cuda()
+    s = fz.compress(xt, 1e-3, "rel")
+    y = fz.decompress(s, x.shape)
+    q = fz.quality(xt, y)
+    r = Q.quality(x, y.cpu().numpy())
+    for k in ("n", "nonfinite", "max_abs_err", "vmin", "vmax"):
+        assert q[k] == r[k], k
+    assert q["mse"] == pytest.approx(r["mse"], rel=1e-9)
+    assert abs(q["psnr"] - r["psnr"]) < 1e-7
+    info = fz.stream_info(s)
+    eb_abs = 1e-3 * (float(info["vmax"]) - float(info["vmin"]))
+    assert q["max_abs_err"] <= eb_abs + 4 * float(np.spacing(np.float32(np.abs(x).max())))
