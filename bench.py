@@ -36,6 +36,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum CPU time of the oracle baseline")
     p.add_argument("--no-layers", action="store_true", help="skip the batched and serving measurements")
+    p.add_argument("--no-ablation", action="store_true", help="skip the per-kernel ablation")
     p.add_argument("--no-quality", action="store_true",
                    help="skip the rate-distortion sweep and the overall-throughput measurement")
     p.add_argument("--batch-fields", type=int, default=256)
@@ -436,6 +437,51 @@ def overall_throughput(xt, shape, eb, s_bytes, t_compr_gbps, steps):
             "paper_links": [{"link_GBps": L, "model_GBps": round(model(L), 2)} for L in PAPER_LINKS_GBPS]}
 
 
+def bench_ablation(xt, inv, t_fused_ms, reps=10):
+    """The paper's per-kernel ablation (Sec. 4.5) on this field: each stage
+    of the unfused pipeline timed with HIP events over `reps` launches, for
+    both dual-quantization versions, both bitshuffle-mark variants and the
+    encoder on either version's tiles."""
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    ab = fz.Ablation(xt)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps  # us
+
+    r = {}
+    for v in (1, 2):
+        r["pred_quant_v%d_us" % v] = timed(lambda: ab.pred_quant(v, inv))
+        ab.bitshuffle_mark()
+        r["encode_v%d_us" % v] = timed(ab.encode)
+        r["nonzero_blocks_v%d" % v] = round(float(ab.offsets[-1].item()) / (ab.steps * 256), 4)
+    # bitshuffle-mark on the v2 codes (the pipeline's state after the loop)
+    ab.pred_quant(2, inv)
+    r["bitshuffle_us"] = timed(ab.bitshuffle)
+    r["mark_us"] = timed(ab.mark)
+    r["bitshuffle_mark_v1_us"] = r["bitshuffle_us"] + r["mark_us"]
+    r["bitshuffle_mark_v2_us"] = timed(ab.bitshuffle_mark)
+    out = {k: (round(v, 1) if k.endswith("_us") else v) for k, v in r.items()}
+    out["speedup_pred_quant"] = round(r["pred_quant_v1_us"] / r["pred_quant_v2_us"], 3)
+    out["speedup_bitshuffle_mark"] = round(r["bitshuffle_mark_v1_us"] / r["bitshuffle_mark_v2_us"], 3)
+    out["speedup_encode"] = round(r["encode_v1_us"] / r["encode_v2_us"], 3)
+    out["unfused_v2_pipeline_us"] = round(r["pred_quant_v2_us"] + r["bitshuffle_mark_v2_us"] + r["encode_v2_us"], 1)
+    out["fused_compress_abs_us"] = round(t_fused_ms * 1e3, 1)
+    del ab
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -537,6 +583,8 @@ def main():
         out["rate_distortion"] = rate_distortion(xt, shape)
         out["overall_throughput"] = overall_throughput(xt, shape, a.eb, s_bytes, in_bytes / 1e9 / (tc * 1e-3),
                                                        a.steps)
+    if not a.no_ablation:
+        out["ablation"] = bench_ablation(xt, float(info["inv"]), tca)
     if not a.no_layers:
         del buf, y
         torch.cuda.empty_cache()

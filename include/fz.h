@@ -267,6 +267,51 @@ size_t fz_quality_work_bytes(const fz_dims *dims);
 int fz_quality(const float *d_x, const float *d_y, const fz_dims *dims, fz_quality_report *d_res, void *d_work,
                void *stream);
 
+/* ----------------------------------------------------------- ablation
+ * The kernel split the paper compares in Sec. 4.5, rebuilt to measure the
+ * same effects on this device; the compression calls above do not use it.
+ * Only 3-D fields whose extents are multiples of the chunk box 16 x 32 x 64
+ * (slowest first) are accepted (others: FZ_ERR_ARG), with finite input and
+ * |x * inv| < 2^31.  A step is one z-plane of one chunk (2048 codes); steps are
+ * numbered chunk by chunk (chunks in row-major order), z-planes in order.
+ *
+ * fz_abl_pred_quant -- dual-quantization with inv = fp32(1 / (2 eb)):
+ * q = rint(x * inv), then the chunk-local Lorenzo difference d (zero outside
+ * the chunk), written per value in the field's row-major order to d_codes
+ * (N u16):
+ *   version 1 (the original scheme, Sec. 2.3): d + 512 when -512 < d < 512,
+ *             else 0, and d_outliers (N int32, required) receives d where the
+ *             code is 0 and 0 elsewhere;
+ *   version 2 (the optimized scheme, Sec. 3.2): the 16-bit sign-magnitude
+ *             code of d, 0x8000 when |d| > 32767; d_outliers is unused. */
+int fz_abl_pred_quant(int version, const float *d_x, const fz_dims *dims, float inv, uint16_t *d_codes,
+                      int32_t *d_outliers, void *stream);
+
+/* fz_abl_bitshuffle -- Sec. 3.3: per step a 4096-byte tile at d_tiles +
+ * 1024 * step (u32 words): word b * 64 + p holds bit b of the 32 codes of
+ * patch p (bit m = cell m; cell m is row m / 8, column m % 8 of the patch;
+ * patch p covers rows 4 * (p % 8) .. + 3 and columns 8 * (p / 8) .. + 7 of the
+ * step).  d_tiles: N / 2 u32. */
+int fz_abl_bitshuffle(const uint16_t *d_codes, const fz_dims *dims, uint32_t *d_tiles, void *stream);
+
+/* fz_abl_mark -- Sec. 3.4: the flags of the tiles: block beta of a step is
+ * words 4 * beta .. 4 * beta + 3 of its tile (plane beta / 16 of 128
+ * consecutive codes); bit beta % 64 of u64 word 4 * step + beta / 64 of
+ * d_flags is set when the block is nonzero.  d_flags: N / 512 u64. */
+int fz_abl_mark(const uint32_t *d_tiles, const fz_dims *dims, uint64_t *d_flags, void *stream);
+
+/* fz_abl_bitshuffle_mark -- the two above fused into one kernel (Sec. 3.3):
+ * the same tiles and flags, the flags taken from the words in registers. */
+int fz_abl_bitshuffle_mark(const uint16_t *d_codes, const fz_dims *dims, uint32_t *d_tiles, uint64_t *d_flags,
+                           void *stream);
+
+/* fz_abl_encode -- Sec. 3.4: d_offsets (steps + 1 u64) receives the exclusive
+ * prefix sum of the per-step nonzero block counts (its last entry the
+ * total); d_out (up to N * 2 bytes) the nonzero 16-byte blocks, step by step
+ * in block order. */
+int fz_abl_encode(const uint32_t *d_tiles, const uint64_t *d_flags, const fz_dims *dims, uint64_t *d_offsets,
+                  void *d_out, void *stream);
+
 /* Parse a host copy of the first n >= 128 bytes of a stream. */
 int fz_stream_info(const void *h_header, size_t n, fz_info *out);
 

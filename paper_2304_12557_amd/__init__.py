@@ -124,6 +124,14 @@ def lib():
         L.fz_quality_work_bytes.restype = ctypes.c_size_t
         L.fz_quality.argtypes = [vp, vp, dp, vp, vp, vp]
         L.fz_quality.restype = ctypes.c_int
+        L.fz_abl_pred_quant.argtypes = [ctypes.c_int, vp, dp, ctypes.c_float, vp, vp, vp]
+        L.fz_abl_bitshuffle.argtypes = [vp, dp, vp, vp]
+        L.fz_abl_mark.argtypes = [vp, dp, vp, vp]
+        L.fz_abl_bitshuffle_mark.argtypes = [vp, dp, vp, vp, vp]
+        L.fz_abl_encode.argtypes = [vp, vp, dp, vp, vp, vp]
+        for name in ("fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark",
+                     "fz_abl_encode"):
+            getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -131,7 +139,8 @@ def lib():
 SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
-           "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality"]
+           "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
+           "fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark", "fz_abl_encode"]
 FZ_REQ_COMPRESS = 0
 FZ_REQ_DECOMPRESS = 1
 
@@ -231,6 +240,58 @@ def quality(x, y, stream=None):
         raise FzError(rc, "fz_quality")
     q = FzQuality.from_buffer_copy(bytes(res.cpu().numpy().tobytes()))
     return {f: getattr(q, f) for f, _ in FzQuality._fields_}
+
+
+class Ablation:
+    """The paper's per-kernel ablation pipeline (fz_abl_* in fz.h) on one 3-D
+    float32 CUDA tensor whose extents are multiples of 16 x 32 x 64; owns the
+    intermediate buffers.  Each method enqueues one stage on ``stream``."""
+
+    def __init__(self, x):
+        import torch
+
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 3):
+            raise ValueError("x must be a contiguous 3-D float32 CUDA tensor")
+        self.x, self.dims = x, dims_of(x.shape)
+        n = x.numel()
+        dev = x.device
+        self.codes = torch.empty(n, dtype=torch.int16, device=dev)
+        self.outliers = torch.empty(n, dtype=torch.int32, device=dev)
+        self.tiles = torch.empty(n // 2, dtype=torch.int32, device=dev)
+        self.steps = n // 2048
+        self.flags = torch.empty(self.steps * 4, dtype=torch.int64, device=dev)
+        self.offsets = torch.empty(self.steps + 1, dtype=torch.int64, device=dev)
+        self.out = torch.empty(n * 2, dtype=torch.uint8, device=dev)
+
+    def _call(self, rc, what):
+        if rc:
+            raise FzError(rc, what)
+
+    def pred_quant(self, version, inv, stream=None):
+        self._call(lib().fz_abl_pred_quant(int(version), ctypes.c_void_p(self.x.data_ptr()), ctypes.byref(self.dims),
+                                           float(inv), ctypes.c_void_p(self.codes.data_ptr()),
+                                           ctypes.c_void_p(self.outliers.data_ptr()), _stream_ptr(stream)),
+                   "fz_abl_pred_quant")
+
+    def bitshuffle(self, stream=None):
+        self._call(lib().fz_abl_bitshuffle(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
+                                           ctypes.c_void_p(self.tiles.data_ptr()), _stream_ptr(stream)),
+                   "fz_abl_bitshuffle")
+
+    def mark(self, stream=None):
+        self._call(lib().fz_abl_mark(ctypes.c_void_p(self.tiles.data_ptr()), ctypes.byref(self.dims),
+                                     ctypes.c_void_p(self.flags.data_ptr()), _stream_ptr(stream)), "fz_abl_mark")
+
+    def bitshuffle_mark(self, stream=None):
+        self._call(lib().fz_abl_bitshuffle_mark(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
+                                                ctypes.c_void_p(self.tiles.data_ptr()),
+                                                ctypes.c_void_p(self.flags.data_ptr()), _stream_ptr(stream)),
+                   "fz_abl_bitshuffle_mark")
+
+    def encode(self, stream=None):
+        self._call(lib().fz_abl_encode(ctypes.c_void_p(self.tiles.data_ptr()), ctypes.c_void_p(self.flags.data_ptr()),
+                                       ctypes.byref(self.dims), ctypes.c_void_p(self.offsets.data_ptr()),
+                                       ctypes.c_void_p(self.out.data_ptr()), _stream_ptr(stream)), "fz_abl_encode")
 
 
 def stream_info(header):

@@ -146,3 +146,22 @@ def test_quality_argument_errors():
     assert L.fz_quality_work_bytes(ctypes.byref(bad)) == 0
     assert L.fz_quality(p, p, ctypes.byref(bad), p, p, None) == 1
     assert ctypes.sizeof(fz.FzQuality) == 56
+
+
+def test_ablation_argument_errors():
+    L = fz.lib()
+    p = ctypes.c_void_p(256)
+    good = fz.dims_of((32, 64, 128))
+    for shape in [(32, 64), (32, 64, 100), (20, 64, 128), (32, 48, 128)]:
+        d = fz.dims_of(shape)
+        assert L.fz_abl_pred_quant(2, p, ctypes.byref(d), 100.0, p, p, None) == 1, shape
+        assert L.fz_abl_bitshuffle(p, ctypes.byref(d), p, None) == 1, shape
+        assert L.fz_abl_mark(p, ctypes.byref(d), p, None) == 1, shape
+        assert L.fz_abl_bitshuffle_mark(p, ctypes.byref(d), p, p, None) == 1, shape
+        assert L.fz_abl_encode(p, p, ctypes.byref(d), p, p, None) == 1, shape
+    assert L.fz_abl_pred_quant(3, p, ctypes.byref(good), 100.0, p, p, None) == 1
+    assert L.fz_abl_pred_quant(1, p, ctypes.byref(good), 100.0, p, None, None) == 1
+    assert L.fz_abl_pred_quant(2, p, ctypes.byref(good), float("inf"), p, None, None) == 1
+    assert L.fz_abl_pred_quant(2, p, ctypes.byref(good), 0.0, p, None, None) == 1
+    assert L.fz_abl_pred_quant(2, None, ctypes.byref(good), 100.0, p, None, None) == 1
+    assert L.fz_abl_encode(p, p, ctypes.byref(good), None, p, None) == 1
