@@ -307,8 +307,9 @@ int fz_abl_bitshuffle_mark(const uint16_t *d_codes, const fz_dims *dims, uint32_
 
 /* fz_abl_encode -- Sec. 3.4: d_offsets (steps + 1 u64) receives the exclusive
  * prefix sum of the per-step nonzero block counts (its last entry the
- * total); d_out (up to N * 2 bytes) the nonzero 16-byte blocks, step by step
- * in block order. */
+ * total); d_out (N * 2 bytes) the nonzero 16-byte blocks, step by step in
+ * block order (its start also holds the per-tile totals of the scan until
+ * the blocks are written). */
 int fz_abl_encode(const uint32_t *d_tiles, const uint64_t *d_flags, const fz_dims *dims, uint64_t *d_offsets,
                   void *d_out, void *stream);
 

@@ -192,38 +192,68 @@ __global__ __launch_bounds__(64) void k_abl_shuffle_mark(const uint16_t* __restr
     if (lane < 4) flags[(int64_t)blockIdx.x * 4 + lane] = lane == 0 ? F[0] : lane == 1 ? F[1] : lane == 2 ? F[2] : F[3];
 }
 
-// prefix sum: block counts per step -> exclusive offsets (one workgroup)
-constexpr int kAblScanThreads = 1024;
+// prefix sum: block counts per step -> exclusive offsets, in tiles of 8192
+// steps, one workgroup each.  Pass 1: thread t counts the 8 consecutive steps
+// 8t .. 8t+7 of its tile (16 loads in flight), the workgroup scans the 1024
+// sums and writes the tile-local offsets and the tile total (to `tot`).
+// Pass 2: each tile adds the totals of the tiles before it.
+constexpr int kAblScanThreads = 1024, kAblScanPer = 8;
+constexpr int64_t kAblScanTile = (int64_t)kAblScanThreads * kAblScanPer;
 
-__global__ __launch_bounds__(kAblScanThreads) void k_abl_scan(const uint64_t* __restrict__ flags, int64_t steps,
-                                                               uint64_t* __restrict__ offsets)
+__global__ __launch_bounds__(kAblScanThreads) void k_abl_scan_local(const uint64_t* __restrict__ flags, int64_t steps,
+                                                                     uint64_t* __restrict__ offsets,
+                                                                     uint64_t* __restrict__ tot)
 {
     __shared__ uint64_t s_wave[kAblScanThreads / 64];
-    __shared__ uint64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int64_t t0 = 0; t0 < steps; t0 += kAblScanThreads) {
-        const int64_t s = t0 + threadIdx.x;
-        uint64_t cnt = 0;
-        if (s < steps)
-            for (int k = 0; k < 4; k++) cnt += (uint64_t)__popcll(flags[4 * s + k]);
-        uint64_t inc = cnt;
+    const int64_t s0 = (int64_t)blockIdx.x * kAblScanTile + (int64_t)threadIdx.x * kAblScanPer;
+    const int64_t n = s0 < steps ? min((int64_t)kAblScanPer, steps - s0) : 0;
+    uint32_t cnt[kAblScanPer];
+    const uint4* f = reinterpret_cast<const uint4*>(flags + 4 * s0);
 #pragma unroll
-        for (int sh = 1; sh < 64; sh <<= 1) {
-            const uint64_t v = __shfl_up(inc, sh);
-            inc += lane >= sh ? v : 0;
-        }
-        if (lane == 63) s_wave[w] = inc;
-        __syncthreads();
-        uint64_t before = s_carry;
-        for (int k = 0; k < w; k++) before += s_wave[k];
-        if (s < steps) offsets[s] = before + inc - cnt;
-        __syncthreads();
-        if (threadIdx.x == kAblScanThreads - 1) s_carry = before + inc;
-        __syncthreads();
+    for (int k = 0; k < kAblScanPer; k++) {
+        const int kk = k < n ? k : 0;  // loads stay inside the flags; out-of-range steps count 0
+        const uint4 a = n > 0 ? f[2 * kk] : make_uint4(0, 0, 0, 0);
+        const uint4 b = n > 0 ? f[2 * kk + 1] : make_uint4(0, 0, 0, 0);
+        const uint32_t c = __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w) + __popc(b.x) + __popc(b.y) +
+                           __popc(b.z) + __popc(b.w);
+        cnt[k] = k < n ? c : 0u;
     }
-    if (threadIdx.x == 0) offsets[steps] = s_carry;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kAblScanPer; k++) sum += cnt[k];
+    uint64_t inc = sum;
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) {
+        const uint64_t v = __shfl_up(inc, sh);
+        inc += lane >= sh ? v : 0;
+    }
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    uint64_t pos = inc - sum;
+    for (int k = 0; k < w; k++) pos += s_wave[k];
+#pragma unroll
+    for (int k = 0; k < kAblScanPer; k++) {
+        if (k < n) offsets[s0 + k] = pos;
+        pos += cnt[k];
+    }
+    if (threadIdx.x == kAblScanThreads - 1) tot[blockIdx.x] = pos;
+}
+
+__global__ __launch_bounds__(kAblScanThreads) void k_abl_scan_fix(int64_t steps, const uint64_t* __restrict__ tot,
+                                                                   uint64_t* __restrict__ offsets)
+{
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) {
+        uint64_t c = 0;
+        for (unsigned i = 0; i < blockIdx.x; i++) c += tot[i];
+        s_carry = c;
+        if (blockIdx.x == gridDim.x - 1) offsets[steps] = c + tot[blockIdx.x];
+    }
+    __syncthreads();
+    const uint64_t carry = s_carry;
+    const int64_t s0 = (int64_t)blockIdx.x * kAblScanTile;
+    for (int64_t i = threadIdx.x; i < kAblScanTile && s0 + i < steps; i += kAblScanThreads) offsets[s0 + i] += carry;
 }
 
 // encode: one wave per step copies its nonzero blocks, in block order, to
@@ -304,7 +334,14 @@ int fz_abl_encode(const uint32_t* d_tiles, const uint64_t* d_flags, const fz_dim
     AblGeom g;
     if (!d_tiles || !d_flags || !d_offsets || !d_out || !abl_geom(dims, &g)) return FZ_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_abl_scan, dim3(1), dim3(kAblScanThreads), 0, st, d_flags, g.steps, d_offsets);
+    // the tile totals wait at the start of d_out, which the compaction only
+    // writes after both scan passes
+    const int64_t tiles = (g.steps + kAblScanTile - 1) / kAblScanTile;
+    uint64_t* tot = static_cast<uint64_t*>(d_out);
+    hipLaunchKernelGGL(k_abl_scan_local, dim3((unsigned)tiles), dim3(kAblScanThreads), 0, st, d_flags, g.steps,
+                       d_offsets, tot);
+    if (done() != hipSuccess) return FZ_ERR_HIP;
+    hipLaunchKernelGGL(k_abl_scan_fix, dim3((unsigned)tiles), dim3(kAblScanThreads), 0, st, g.steps, tot, d_offsets);
     if (done() != hipSuccess) return FZ_ERR_HIP;
     hipLaunchKernelGGL(k_abl_encode, dim3((unsigned)g.steps), dim3(64), 0, st, d_tiles, d_flags, d_offsets,
                        static_cast<uint4*>(d_out));
