@@ -34,28 +34,33 @@ __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, 
     return 0;
 }
 
-__device__ __forceinline__ void decode_codes(const uint32_t (&P)[16], int (&d)[32])
+// Sign-magnitude decode (Sec. 3.2).  The transpose ran with plane 15 (the
+// signs) cleared, so P[i] holds the magnitudes of codes i and i+16; bit m of
+// `sgn` is the sign of code m.  d = (m ^ s) - s with s = 0 or -1.
+__device__ __forceinline__ void decode_codes(const uint32_t (&P)[16], uint32_t sgn, int (&d)[32])
 {
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        const uint32_t lo = P[i] & 0xFFFFu, hi = P[i] >> 16;
-        const int mlo = (int)(lo & 0x7FFFu), mhi = (int)(hi & 0x7FFFu);
-        d[i] = (lo & 0x8000u) ? -mlo : mlo;
-        d[i + 16] = (hi & 0x8000u) ? -mhi : mhi;
+        const int slo = (int)(sgn << (31 - i)) >> 31, shi = (int)(sgn << (15 - i)) >> 31;
+        const int mlo = (int)(P[i] & 0xFFFFu), mhi = (int)(P[i] >> 16);
+        d[i] = (mlo ^ slo) - slo;
+        d[i + 16] = (mhi ^ shi) - shi;
     }
 }
 
 // Replace escaped cells (code 0x8000) by their logged deltas.  Pairs are in
 // code-index order: this step's pairs follow the `seen` earlier ones.
-__device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], int (&d)[32], const uint32_t* __restrict__ pairs,
-                                               uint32_t nout, uint32_t& seen, uint32_t n0, int lane)
+__device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], uint32_t sgn, int (&d)[32],
+                                                  const uint32_t* __restrict__ pairs, uint32_t nout, uint32_t& seen,
+                                                  uint32_t n0, int lane)
 {
-    uint32_t emask = 0;
+    uint32_t emask = 0;  // the escape code 0x8000: sign set, magnitude 0
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        emask |= ((P[i] & 0xFFFFu) == kEscape ? 1u : 0u) << i;
-        emask |= ((P[i] >> 16) == kEscape ? 1u : 0u) << (i + 16);
+        emask |= ((P[i] & 0xFFFFu) == 0u ? 1u : 0u) << i;
+        emask |= ((P[i] >> 16) == 0u ? 1u : 0u) << (i + 16);
     }
+    emask &= sgn;
     const int cnt = __popc(emask);
     const int incl = wave_incl_scan(cnt, lane);
     const uint32_t total = (uint32_t)__shfl(incl, 63);
@@ -194,11 +199,13 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             if (k < 0 || step_lo >= ext[0]) continue;
             uint32_t P[16];
 #pragma unroll
-            for (int b = 0; b < 16; b++) P[b] = W[t][b];
+            for (int b = 0; b < 15; b++) P[b] = W[t][b];
+            const uint32_t sgn = W[t][15];  // plane 15: the signs
+            P[15] = 0u;
             transpose16(P);
             int d[32];
-            decode_codes(P, d);
-            if (nout) esc_bad |= apply_escapes(P, d, pairs, nout, seen, (uint32_t)st * kStepCodes, lane);
+            decode_codes(P, sgn, d);
+            if (nout) esc_bad |= apply_escapes(P, sgn, d, pairs, nout, seen, (uint32_t)st * kStepCodes, lane);
 
             if (RANK == 3) {
                 // prefix along x inside the patch, carry across the lanes 8 apart (DPP and lane swaps)
