@@ -21,6 +21,9 @@
  *   - zero-block encoder (bit flag per data block, prefix sum of block counts
  *     for offsets, copy of the nonzero blocks): Sec. 3.4;
  *   - value-range-relative error bound: Sec. 4.1 ("Baselines");
+ *   - point-wise relative error bound through a logarithmic transform of the
+ *     data, compressed with the absolute bound that the relative bound
+ *     implies: Sec. 4.1 ("Datasets", the HACC treatment);
  *   - decompression is the symmetric inverse: Sec. 4.4.
  * The paper leaves the chunk shape, the order of codes inside a tile, the
  * handling of codes that do not fit in 16 bits, and the stream layout open;
@@ -163,6 +166,15 @@ int64_t fzo_bound(int rank, const int64_t *dims)
 int fzo_eb_params(const float *x, int64_t n, double eb, int eb_mode,
                   float *ebx2, float *inv, float *vmin, float *vmax)
 {
+    if (eb_mode == FZO_EB_PWREL) {
+        /* PWREL: the step S = floor(eb * 2^24 / (1 + eb)) of the transformed
+         * values (see O2b), recorded as an exact float in the ebx2 slot; inv
+         * is 0.  Valid for 2 <= S < 2^24. */
+        double sd = floor(eb * 16777216.0 / (1.0 + eb));
+        *vmin = 0.0f; *vmax = 0.0f; *inv = 0.0f;
+        *ebx2 = (sd >= 2.0 && sd < 16777216.0) ? (float)sd : 0.0f;
+        return (sd >= 2.0 && sd < 16777216.0) ? 0 : FZO_ERR_EB_RANGE;
+    }
     float lo = 0.0f, hi = 0.0f;
     int status = 0;
     if (n > 0 && eb_mode == FZO_EB_REL) { lo = x[0] == 0.0f ? 0.0f : x[0]; hi = lo; }
@@ -205,6 +217,48 @@ int fzo_prequant(const float *x, int64_t n, float inv, int32_t *q)
         q[i] = (int32_t)rintf(p);
     }
     return status;
+}
+
+/* ---------------------------------- O2b: the point-wise relative mode
+ * The logarithmic transform is the float's own bit pattern: for a finite x,
+ * T(x) = b with b = the 31 low bits of x (exponent and mantissa) and the sign
+ * of x, which is 2^23 (log2|x| + 127) at every power of two and linear in
+ * between.  Quantizing T with the absolute step S changes b by at most S / 2.
+ * Within a binade that changes x by a factor of at most 1 + S / 2^24; a change
+ * that crosses into the next binade up (where the slope doubles) by at most
+ * (S / 2^24) / (1 - S / 2^25).  S = floor(eps * 2^24 / (1 + eps)) gives
+ * S / 2^24 <= eps / (1 + eps), which keeps both within 1 + eps / (1 + eps / 2)
+ * <= 1 + eps, so |x' - x| <= eps * |x| for normal x; for denormal x
+ * (linear bits, no exponent) the change is at most S / 2 units of 2^-149,
+ * below eps * 2^-126.
+ *   q = sign(x) * floor((b + floor(S / 2)) / S)
+ *   x' = the float with the sign of q and the bits min(|q| * S, 0x7F7FFFFF).
+ * Zeros of either sign give q = 0 and x' = +0; NaN and infinities are
+ * non-finite input.                                                      */
+int fzo_prequant_pw(const float *x, int64_t n, uint32_t step, int32_t *q)
+{
+    int status = 0;
+    for (int64_t i = 0; i < n; i++) {
+        float v = x[i];
+        if (!isfinite(v)) { status |= FZO_ERR_NONFINITE; q[i] = 0; continue; }
+        uint32_t bits;
+        memcpy(&bits, &v, 4);
+        uint32_t b = bits & 0x7FFFFFFFu;
+        uint32_t a = (b + step / 2u) / step;
+        q[i] = (bits >> 31) ? -(int32_t)a : (int32_t)a;
+    }
+    return status;
+}
+
+float fzo_dequant_pw(int32_t q, uint32_t step)
+{
+    uint64_t a = q < 0 ? (uint64_t)(-(int64_t)q) : (uint64_t)q;
+    uint64_t m = a * (uint64_t)step;
+    if (m > 0x7F7FFFFFu) m = 0x7F7FFFFFu;
+    uint32_t bits = (uint32_t)m | (q < 0 ? 0x80000000u : 0u);
+    float v;
+    memcpy(&v, &bits, 4);
+    return v;
 }
 
 /* ------------------------------------------- O3: chunk-local Lorenzo on q
@@ -347,7 +401,8 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
 {
     geom_t g;
     if (make_geom(rank, dims, &g)) return -1;
-    if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != FZO_EB_ABS && eb_mode != FZO_EB_REL)) return -1;
+    if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != FZO_EB_ABS && eb_mode != FZO_EB_REL && eb_mode != FZO_EB_PWREL))
+        return -1;
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     int64_t H = header_bytes(&g);
     if (cap < H) return -1;
@@ -355,7 +410,9 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
     float ebx2, inv, vmin, vmax;
     uint32_t status = (uint32_t)fzo_eb_params(x, N, eb, eb_mode, &ebx2, &inv, &vmin, &vmax);
     int32_t *q = (int32_t *)calloc((size_t)N, sizeof(int32_t));
-    if (!status) status |= (uint32_t)fzo_prequant(x, N, inv, q);
+    if (!status)
+        status |= (uint32_t)(eb_mode == FZO_EB_PWREL ? fzo_prequant_pw(x, N, (uint32_t)ebx2, q)
+                                                     : fzo_prequant(x, N, inv, q));
 
     chunk_out_t *co = (chunk_out_t *)calloc((size_t)g.n_chunks, sizeof(chunk_out_t));
     if (!status) {
@@ -436,7 +493,8 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
  * D1 parse/validate, D2-D3 rebuild the codes of each chunk from the flags
  * and bricks, D4 codes -> delta (escapes take the chunk's pairs), D5 the
  * inverse Lorenzo = inclusive prefix sums along x, then y, then z inside the
- * chunk box (mod 2^32), D6 x' = fp32((float)q * ebx2).                    */
+ * chunk box (mod 2^32), D6 x' = fp32((float)q * ebx2), or in PWREL mode the
+ * inverse transform of q * S (O2b).                                       */
 int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims)
 {
     geom_t g;
@@ -454,6 +512,15 @@ int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int
     if (total > size || total < H) return FZO_DERR_STREAM;
     float ebx2;
     memcpy(&ebx2, s + 48, 4);
+    /* the bound mode: 0 ABS, 1 REL (x' = q * ebx2), 2 PWREL (x' from the
+     * transformed value q * S, S recorded in the ebx2 slot) */
+    int mode = s[14];
+    if (mode > FZO_EB_PWREL) return FZO_DERR_STREAM;
+    uint32_t step = 0;
+    if (mode == FZO_EB_PWREL) {
+        if (!(ebx2 >= 2.0f && ebx2 < 16777216.0f) || ebx2 != floorf(ebx2)) return FZO_DERR_STREAM;
+        step = (uint32_t)ebx2;
+    }
     const uint8_t *flags = s + H - (int64_t)FZO_FLAG_BYTES_PER_CHUNK * g.n_chunks;
     const uint8_t *payload = s + H;
     int64_t payload_units = (total - H) / 16;
@@ -530,7 +597,9 @@ int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int
         for (int64_t a = 0; a < e0; a++)
             for (int64_t b = 0; b < e1; b++)
                 for (int64_t cc = 0; cc < e2; cc++)
-                    x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
+                    x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] =
+                        mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)box[(a * e1 + b) * e2 + cc], step)
+                                             : (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
     }
     free(codes); free(delta); free(box);
     if (!err && H + 16 * units_seen != total) err = FZO_DERR_STREAM;

@@ -8,6 +8,7 @@
 
 #define FZO_EB_ABS 0
 #define FZO_EB_REL 1
+#define FZO_EB_PWREL 2
 
 /* data-dependent error bits (OR-ed into the stream header status word) */
 #define FZO_ERR_NONFINITE 1u
@@ -26,6 +27,8 @@ int64_t fzo_n_chunks(int rank, const int64_t *dims);
 int fzo_eb_params(const float *x, int64_t n, double eb, int eb_mode, float *ebx2, float *inv, float *vmin,
                   float *vmax);
 int fzo_prequant(const float *x, int64_t n, float inv, int32_t *q);
+int fzo_prequant_pw(const float *x, int64_t n, uint32_t step, int32_t *q);
+float fzo_dequant_pw(int32_t q, uint32_t step);
 int fzo_code_of(int32_t d, uint16_t *code);
 int32_t fzo_delta_of(uint16_t code);
 int fzo_lorenzo_field(const int32_t *q, int rank, const int64_t *dims, int32_t *delta);

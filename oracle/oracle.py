@@ -15,6 +15,7 @@ _LIB = None
 
 EB_ABS = 0
 EB_REL = 1
+EB_PWREL = 2
 ERR_NONFINITE = 1
 ERR_EB_RANGE = 2
 ERR_OUTLIER_CAP = 4
@@ -44,6 +45,10 @@ def lib():
         L.fzo_eb_params.restype = ctypes.c_int
         L.fzo_prequant.argtypes = [vp, ctypes.c_int64, ctypes.c_float, vp]
         L.fzo_prequant.restype = ctypes.c_int
+        L.fzo_prequant_pw.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, vp]
+        L.fzo_prequant_pw.restype = ctypes.c_int
+        L.fzo_dequant_pw.argtypes = [ctypes.c_int32, ctypes.c_uint32]
+        L.fzo_dequant_pw.restype = ctypes.c_float
         L.fzo_code_of.argtypes = [ctypes.c_int32, vp]
         L.fzo_code_of.restype = ctypes.c_int
         L.fzo_delta_of.argtypes = [ctypes.c_uint16]
@@ -97,6 +102,17 @@ def prequant(x, inv):
     q = np.zeros(x.shape, dtype=np.int32)
     st = lib().fzo_prequant(_ptr(x), x.size, np.float32(inv), _ptr(q))
     return q, st
+
+
+def prequant_pw(x, step):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.zeros(x.shape, dtype=np.int32)
+    st = lib().fzo_prequant_pw(_ptr(x), x.size, int(step), _ptr(q))
+    return q, st
+
+
+def dequant_pw(q, step):
+    return np.float32(lib().fzo_dequant_pw(int(q), int(step)))
 
 
 def code_of(d):
