@@ -41,14 +41,16 @@ typedef enum {
     FZ_ERR_ARG = 1,          /* invalid argument (returned immediately) */
     FZ_ERR_HIP = 2,          /* a HIP runtime call failed */
     FZ_ERR_NONFINITE = 3,    /* input holds NaN or Inf */
-    FZ_ERR_EB_RANGE = 4,     /* error bound unusable: 2*eb not a normal fp32, or |x/(2eb)| >= 2^31 */
+    FZ_ERR_EB_RANGE = 4,     /* error bound unusable: 2*eb not a normal fp32, or |x/(2eb)| >= 2^31;
+                              * FZ_EB_PWREL: the step (see fz_compress) outside [2, 2^24) */
     FZ_ERR_OUTLIER_CAP = 5,  /* more than 256 escaped codes in one layer of 8192 codes */
     FZ_ERR_STREAM = 6,       /* malformed or inconsistent stream */
     FZ_ERR_VERSION = 7,      /* unknown stream version */
     FZ_ERR_STATUS = 8        /* stream carries a nonzero compression status */
 } fz_status;
 
-typedef enum { FZ_EB_ABS = 0, FZ_EB_REL = 1 } fz_eb_mode;
+/* FZ_EB_PWREL: point-wise relative bound (see fz_compress). */
+typedef enum { FZ_EB_ABS = 0, FZ_EB_REL = 1, FZ_EB_PWREL = 2 } fz_eb_mode;
 
 /* Field extents, slowest-varying first (a 3-D field 100 x 500 x 500 has
  * n = {100, 500, 500}; x is the contiguous dimension).  rank is 1, 2 or 3;
@@ -72,8 +74,8 @@ typedef struct {
     uint32_t eb_mode;
     uint64_t n[3];
     double eb_user;
-    float ebx2;           /* fp32(2 * absolute error bound) */
-    float inv;            /* fp32(1 / ebx2) */
+    float ebx2;           /* fp32(2 * absolute error bound); FZ_EB_PWREL: the step S */
+    float inv;            /* fp32(1 / ebx2); FZ_EB_PWREL: 0 */
     float vmin, vmax;     /* value range (REL mode; 0 in ABS mode) */
     uint32_t n_chunks;
     uint64_t nnz_blocks;  /* nonzero 16-byte blocks stored */
@@ -103,16 +105,28 @@ size_t fz_header_bytes(const fz_dims *dims);
  * REL mode first reads it once more for the value range).
  *   d_in   : N fp32 values, row-major, slowest-first dims (device, read only)
  *   dims   : host pointer
- *   eb     : absolute error bound (FZ_EB_ABS) or bound relative to the value
- *            range max-min (FZ_EB_REL, Sec. 4.1); must be finite and > 0
+ *   eb     : absolute error bound (FZ_EB_ABS), bound relative to the value
+ *            range max-min (FZ_EB_REL, Sec. 4.1), or point-wise relative
+ *            bound eps (FZ_EB_PWREL, below); must be finite and > 0
  *   d_out  : device buffer of at least fz_compress_bound(dims) bytes; on
  *            completion it starts with the stream, whose size is the header's
  *            total_bytes field (little-endian u64 at byte 96)
  * Every reconstructed value differs from the input by at most the error bound
  * (Sec. 2.3 inequality) up to fp32 rounding of x/(2eb) and of q*2eb.
+ * FZ_EB_PWREL (the point-wise relative mode, an extension of Sec. 2.3 to a
+ * transformed field): the pipeline runs on T(x) = sign(x) * (bits of |x|),
+ * an exact integer piecewise-linear log2, with the step S = floor(eps *
+ * 2^24 / (1 + eps)) in place of 2eb, q = sign(x) * floor((T + S/2) / S); the
+ * reconstruction is the float with bits min(|q| * S, largest finite) and q's
+ * sign, so |x' - x| <= eps * max(|x|, 2^-126) for every value, in integer
+ * arithmetic with no rounding.  S must lie in [2, 2^24) (eps from about
+ * 1.2e-7 to any larger value), else FZ_ERR_EB_RANGE at once.  A sign change
+ * between neighbours is a large difference of T and costs an escape, so
+ * fields that cross zero often may hit the escape cap; -0 comes back as +0.
  * Data-dependent errors (NaN/Inf, |x/(2eb)| >= 2^31, escape cap) set bits of
  * the header's status word (u32 at byte 8); the rest of the stream is then
- * unspecified.  Returns FZ_OK once the work is enqueued. */
+ * unspecified.  The first two end the pipeline at prequantization: when
+ * either is set, the escape-cap bit is not.  Returns FZ_OK once the work is enqueued. */
 int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
 
 /* fz_decompress -- the inverse pipeline (Sec. 4.4 describes it as symmetric
@@ -143,7 +157,7 @@ typedef struct {
     const float *d_in;   /* N fp32 values (device) */
     fz_dims dims;
     double eb;
-    int32_t eb_mode;     /* FZ_EB_ABS or FZ_EB_REL */
+    int32_t eb_mode;     /* FZ_EB_ABS or FZ_EB_REL (FZ_EB_PWREL: FZ_ERR_ARG) */
     int32_t reserved;
     void *d_out;         /* fz_compress_bound(&dims) bytes (device) */
 } fz_compress_job;
@@ -193,7 +207,7 @@ int fz_batch_destroy(fz_batch *b);
 
 typedef struct {
     int32_t kind;        /* FZ_REQ_COMPRESS or FZ_REQ_DECOMPRESS */
-    int32_t eb_mode;     /* compress: FZ_EB_ABS or FZ_EB_REL */
+    int32_t eb_mode;     /* compress: FZ_EB_ABS or FZ_EB_REL (FZ_EB_PWREL: FZ_ERR_ARG) */
     double eb;           /* compress: the error bound */
     fz_dims dims;
     const void *d_in;    /* compress: N fp32 values; decompress: the stream */

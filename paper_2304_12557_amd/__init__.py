@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfzmi.so")
 
 FZ_EB_ABS = 0
 FZ_EB_REL = 1
+FZ_EB_PWREL = 2
 STATUS_NONFINITE = 1
 STATUS_EB_RANGE = 2
 STATUS_OUTLIER_CAP = 4
@@ -177,7 +178,9 @@ def _mode(mode):
         return FZ_EB_REL
     if mode in ("abs", FZ_EB_ABS):
         return FZ_EB_ABS
-    raise ValueError("mode must be 'rel' or 'abs'")
+    if mode in ("pwrel", FZ_EB_PWREL):
+        return FZ_EB_PWREL
+    raise ValueError("mode must be 'rel', 'abs' or 'pwrel'")
 
 
 def compress(x, eb, mode="rel", out=None, stream=None):

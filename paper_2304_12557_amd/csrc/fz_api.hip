@@ -62,6 +62,27 @@ bool abs_params(double eb, float* ebx2, float* inv)
     return *ebx2 >= FLT_MIN && std::isfinite(*ebx2) && std::isfinite(*inv) && *inv > 0.0f;
 }
 
+int bound_params(double eb, int mode, float* ebx2, float* inv)
+{
+    *ebx2 = 0.0f;
+    *inv = 0.0f;
+    if (!(eb > 0.0) || !std::isfinite(eb)) return FZ_ERR_ARG;
+    switch (mode) {
+        case FZ_EB_ABS: return abs_params(eb, ebx2, inv) ? FZ_OK : FZ_ERR_EB_RANGE;
+        case FZ_EB_REL: return FZ_OK;
+        case FZ_EB_PWREL: {
+            // the largest step whose half keeps every value within the
+            // relative bound, also across a binade boundary (where the
+            // mantissa's weight doubles): S / 2^24 <= eb / (1 + eb)
+            const double step = std::floor(eb * 16777216.0 / (1.0 + eb));
+            if (!(step >= 2.0 && step < 16777216.0)) return FZ_ERR_EB_RANGE;
+            *ebx2 = (float)step;  // exact: below 2^24
+            return FZ_OK;
+        }
+        default: return FZ_ERR_ARG;
+    }
+}
+
 }  // namespace fz
 
 extern "C" {
@@ -84,12 +105,11 @@ int fz_compress(const float* d_in, const fz_dims* dims, double eb, int eb_mode, 
 {
     Geom g;
     if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
-    if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != FZ_EB_ABS && eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
     float ebx2 = 0.0f, inv = 0.0f;
-    if (eb_mode == FZ_EB_ABS && !abs_params(eb, &ebx2, &inv)) return FZ_ERR_EB_RANGE;
+    const int rc = bound_params(eb, eb_mode, &ebx2, &inv);
+    if (rc != FZ_OK) return rc;
     const HeaderImage h = header_image(g, eb, eb_mode, ebx2, inv);
-    hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode == FZ_EB_REL, eb,
-                                   static_cast<hipStream_t>(stream));
+    hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         const Geom g = J.g;
         const int64_t c = t - J.chunk0;
         const bool skip = reinterpret_cast<const Scratch*>(J.out + g.scratch_off)->pre_status != 0;
-        const float inv = *reinterpret_cast<const float*>(J.out + kOffInv);
+        const Quant inv = quant_of(J.out);
         const Lane l = lane_geo<RANK>(g, c, lane);
         if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         uint32_t tk;  // the next ticket, taken early by thread 0 (its return has the layer to arrive)
@@ -145,12 +145,12 @@ __global__ __launch_bounds__(64) void k_batch_decompress(const DecompressJob* __
     const int64_t c = (int64_t)blockIdx.x - J.chunk0;
     const int lane = threadIdx.x;
     switch (J.key) {
-        case 7: decompress_chunk<3, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 6: decompress_chunk<3, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 5: decompress_chunk<2, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 4: decompress_chunk<2, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 3: decompress_chunk<1, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        default: decompress_chunk<1, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 7: decompress_chunk_any<3, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 6: decompress_chunk_any<3, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 5: decompress_chunk_any<2, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 4: decompress_chunk_any<2, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 3: decompress_chunk_any<1, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        default: decompress_chunk_any<1, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
     }
 }
 

@@ -11,12 +11,13 @@
 // its offset.  REL mode runs k_minmax + k_params first (the value range).
 #include <hip/hip_runtime.h>
 
+#include "fz.h"
 #include "fz_compress_dev.hpp"
 #include "fz_kernels.hpp"
 
 namespace fz {
 
-template <int RANK, bool VEC4>
+template <int RANK, bool VEC4, bool PW>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
 {
     __shared__ CompressLds S;
@@ -24,7 +25,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keep it scalar
     if (scr->pre_status) return;  // set before this launch: uniform across the grid
-    const float inv = *reinterpret_cast<const float*>(out + kOffInv);
+    const Quant inv = quant_of(out);
 
     if (threadIdx.x == 0) {
         S.ticket = atomicAdd(&scr->ticket, 1u);
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         uint32_t tk;  // thread 0 only: a value on the other lanes would need a copy that waits for the atomic
         if (threadIdx.x == 0) tk = atomicAdd(&scr->ticket, 1u);
         uint64_t F[16], myflag;
-        const int nout = chunk_layer<RANK, VEC4>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        const int nout = chunk_layer<RANK, VEC4, PW>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
         if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -86,18 +87,19 @@ int64_t minmax_blocks(int64_t n)
     return blocks < 1 ? 1 : blocks;
 }
 
-template <int RANK, bool VEC4>
+template <int RANK, bool VEC4, bool PW>
 static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
     // persistent grid: as many workgroups as stay resident, at most one per chunk
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4, PW>, 256, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     const int64_t resident = (int64_t)cus * per_cu;
     const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
-    hipLaunchKernelGGL((k_compress<RANK, VEC4>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
+    hipLaunchKernelGGL((k_compress<RANK, VEC4, PW>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, out, g);
@@ -106,7 +108,7 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, bool rel, double eb,
+hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
                            hipStream_t st)
 {
     const int64_t init_threads = g.n_chunks > kHeaderBytes / 4 ? g.n_chunks : kHeaderBytes / 4;
@@ -114,7 +116,7 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
     hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, out, g, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (rel) {
+    if (mode == FZ_EB_REL) {
         const int64_t n = g.n[0] * g.n[1] * g.n[2];
         const int64_t blocks = minmax_blocks(n);
         hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
@@ -123,13 +125,23 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
+    if (mode == FZ_EB_PWREL) {
+        switch (g.rank * 2 + (vec4 ? 1 : 0)) {
+            case 7: return launch_rank<3, true, true>(x, out, g, st);
+            case 6: return launch_rank<3, false, true>(x, out, g, st);
+            case 5: return launch_rank<2, true, true>(x, out, g, st);
+            case 4: return launch_rank<2, false, true>(x, out, g, st);
+            case 3: return launch_rank<1, true, true>(x, out, g, st);
+            default: return launch_rank<1, false, true>(x, out, g, st);
+        }
+    }
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true>(x, out, g, st);
-        case 6: return launch_rank<3, false>(x, out, g, st);
-        case 5: return launch_rank<2, true>(x, out, g, st);
-        case 4: return launch_rank<2, false>(x, out, g, st);
-        case 3: return launch_rank<1, true>(x, out, g, st);
-        default: return launch_rank<1, false>(x, out, g, st);
+        case 7: return launch_rank<3, true, false>(x, out, g, st);
+        case 6: return launch_rank<3, false, false>(x, out, g, st);
+        case 5: return launch_rank<2, true, false>(x, out, g, st);
+        case 4: return launch_rank<2, false, false>(x, out, g, st);
+        case 3: return launch_rank<1, true, false>(x, out, g, st);
+        default: return launch_rank<1, false, false>(x, out, g, st);
     }
 }
 

@@ -73,14 +73,21 @@ __device__ __forceinline__ bool finish_step(const int (&d)[32], uint32_t (&P)[16
 // prequantize 32 values; `facc` tracks max |p| with NaN propagating
 // (v_maximum3_f32), so one compare per step (!(facc < 2^31)) finds NaN, Inf
 // or an overflowing product
-__device__ __forceinline__ void prequant32(const float (&v)[32], float inv, float& facc, int (&q)[32])
+template <bool PW>
+__device__ __forceinline__ void prequant32(const float (&v)[32], const Quant& z, float& facc, int (&q)[32])
 {
+    const float inv = z.inv;  // 0 in the point-wise mode: x * inv flags NaN/Inf there
 #pragma unroll
     for (int i = 0; i < 32; i += 2) {
         const float p0 = v[i] * inv, p1 = v[i + 1] * inv;
         facc = __builtin_elementwise_maximum(facc, __builtin_elementwise_maximum(__builtin_fabsf(p0), __builtin_fabsf(p1)));
-        q[i] = (int)__builtin_rintf(p0);
-        q[i + 1] = (int)__builtin_rintf(p1);
+        if constexpr (PW) {
+            q[i] = pw_quant(v[i], z);
+            q[i + 1] = pw_quant(v[i + 1], z);
+        } else {
+            q[i] = (int)__builtin_rintf(p0);
+            q[i + 1] = (int)__builtin_rintf(p1);
+        }
     }
 }
 
@@ -273,8 +280,8 @@ __device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const
 // nz[b] collects their OR for the flags.
 // Returns whether some delta of the layer needs an escape (only the ESC pass
 // logs them).
-template <int RANK, bool EDGE, bool VEC4, bool ESC>
-__device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
+template <int RANK, bool EDGE, bool VEC4, bool ESC, bool PW = false>
+__device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, Quant inv,
                                       int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
                                       float& facc, EscapeLog& log)
 {
@@ -291,13 +298,14 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
         for (int i = 0; i < 32; i++) qprev[i] = 0;
         if (RANK == 1 && k > 0) {
             uint32_t dummy = 0;
-            carry1 = prequant(x[l.org[0] + (int64_t)kStepCodes * 4 * k - 1], inv, dummy);
+            const float xh = x[l.org[0] + (int64_t)kStepCodes * 4 * k - 1];
+            carry1 = PW ? pw_quant(xh, inv) : prequant(xh, inv.inv, dummy);
         }
     } else if (RANK == 3) {
-        prequant32(h, inv, facc, qprev);
+        prequant32<PW>(h, inv, facc, qprev);
     } else {
         int qh[32];
-        prequant32(h, inv, facc, qh);
+        prequant32<PW>(h, inv, facc, qh);
 #pragma unroll
         for (int c = 0; c < 16; c++) qprev[c] = qh[16 + c];
     }
@@ -325,7 +333,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
         // arithmetic up to its loads, which would wait on them right away
         __builtin_amdgcn_sched_barrier(0);
         int q[32];
-        prequant32(v, inv, facc, q);
+        prequant32<PW>(v, inv, facc, q);
         int d[32];
         if (RANK == 3) {
             int a[32];
@@ -381,8 +389,8 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
 // step of the layer and `v` the one below it.  The deltas and words are those
 // of the forward sweep; escapes are only detected (the out-of-line pass logs
 // them in code order).
-template <int RANK, bool VEC4>
-__device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geom& g, const Lane& l, int k, float inv,
+template <int RANK, bool VEC4, bool PW = false>
+__device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geom& g, const Lane& l, int k, Quant inv,
                                           int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
                                           float& facc, EscapeLog& log)
 {
@@ -391,7 +399,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
 #pragma unroll
     for (int b = 0; b < 16; b++) nz[b] = 0u;
     int cq[32];  // q of the step being coded (3-D: its plane; 2-D: its two rows)
-    prequant32(h, inv, facc, cq);
+    prequant32<PW>(h, inv, facc, cq);
 #pragma unroll
     for (int it = 0; it < 4; it++) {
         const int t = 3 - it, s = 4 * k + t;
@@ -399,7 +407,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
         if (it < 3) load_step<RANK, false, VEC4>(x, g, l, s - 2, lane, vn);  // s - 2 = 4k - 1 at it = 2: the halo
         __builtin_amdgcn_sched_barrier(0);
         int ql[32];  // q of step s - 1
-        prequant32(v, inv, facc, ql);
+        prequant32<PW>(v, inv, facc, ql);
         int d[32];
         if (RANK == 3) {
             int a[32];
@@ -476,9 +484,9 @@ __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom
 // in the scratch so that nothing large crosses the call.  It stays a real
 // call: inlined, its registers would push the fast path into spills, while
 // as a call the register saves happen only on this path.
-template <int RANK, bool VEC4>
+template <int RANK, bool VEC4, bool PW = false>
 __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
-                                            int64_t c, int k, float inv, int lane, uint32_t* Wl, uint32_t* oidx,
+                                            int64_t c, int k, Quant inv, int lane, uint32_t* Wl, uint32_t* oidx,
                                             int32_t* oval)
 {
     const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
@@ -488,8 +496,8 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
     uint32_t nz[16];
     float facc = 0.0f;
     EscapeLog log{oidx, oval, 0};
-    if (l.edge) layer<RANK, true, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    else layer<RANK, false, VEC4, true>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    if (l.edge) layer<RANK, true, VEC4, true, PW>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    else layer<RANK, false, VEC4, true, PW>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     return ((uint64_t)(uint32_t)log.count << 32) | __float_as_uint(facc);
 }
 
@@ -497,7 +505,7 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
 // cells and classify them the way the format defines the status bits
 // (halo values belong to the previous layer, which reports them).
 __device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
-                                                 int64_t c, int k, float inv, int lane)
+                                                 int64_t c, int k, Quant inv, int lane)
 {
     const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
     int64_t o[3], e[3];
@@ -513,7 +521,7 @@ __device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x,
             if (r0 >= e[0] || r1 >= e[1] || r2 >= e[2]) continue;
             const float v = x[((o[0] + r0) * g.n[1] + o[1] + r1) * g.n[2] + o[2] + r2];
             if (!__builtin_isfinite(v)) err |= kErrNonfinite;
-            else if (!(__builtin_fabsf(v * inv) < 2147483648.0f)) err |= kErrEbRange;
+            else if (!(__builtin_fabsf(v * inv.inv) < 2147483648.0f)) err |= kErrEbRange;
         }
     }
     return err;
@@ -538,7 +546,7 @@ struct CompressLds {
 // `myflag`, which chunk_place stores), and the layer's counts in S.  Returns
 // the layer's escape count.
 __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
-                                           int64_t c, int wave, int lane, float inv, const uint32_t (&nz)[16],
+                                           int64_t c, int wave, int lane, Quant inv, const uint32_t (&nz)[16],
                                            float facc, const EscapeLog& log, CompressLds& S, uint64_t (&F)[16],
                                            uint64_t& myflag)
 {
@@ -573,9 +581,9 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 // unless the chunk is cut by the field's edge (the out-of-line pass then
 // loads its own).  F receives the layer's per-plane ballots and `myflag` the
 // flag word lane b < 16 stores; returns the layer's logged escape count.
-template <int RANK, bool VEC4>
+template <int RANK, bool VEC4, bool PW = false>
 __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
-                                           int64_t c, const Lane& l, int wave, int lane, float inv, float (&h)[32],
+                                           int64_t c, const Lane& l, int wave, int lane, Quant inv, float (&h)[32],
                                            float (&v)[32], CompressLds& S, uint64_t (&F)[16], uint64_t& myflag)
 {
     uint32_t nz[16];
@@ -587,14 +595,14 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
         if (!slow) {
             if constexpr (RANK >= 2) {
                 slow = swept_down<RANK>(wave)
-                           ? layer_rev<RANK, VEC4>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
-                           : layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+                           ? layer_rev<RANK, VEC4, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
+                           : layer<RANK, false, VEC4, false, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
             } else {
-                slow = layer<RANK, false, VEC4, false>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+                slow = layer<RANK, false, VEC4, false, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
             }
         }
         if (slow) {  // edge chunk, or escapes to log
-            const uint64_t r = layer_slow<RANK, VEC4>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
+            const uint64_t r = layer_slow<RANK, VEC4, PW>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
             log.count = (int)(r >> 32);
             facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
 #pragma unroll
@@ -841,7 +849,14 @@ __device__ __forceinline__ void scan_field(uint8_t* __restrict__ out, const Geom
     bad = __syncthreads_or(bad);
     if (tid == 0) {
         *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * carry;
-        if (bad) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
+        // every chunk is done: a failed prequantization anywhere (NaN/Inf,
+        // overflow) ends the pipeline before the encoder, so the escape-cap
+        // bit of chunks that went on counts only when no such bit is set
+        uint32_t* st = reinterpret_cast<uint32_t*>(out + kOffStatus);
+        uint32_t v = *st;
+        if (v & (kErrNonfinite | kErrEbRange)) v &= ~kErrOutlierCap;
+        if (bad) v |= kErrInternal;
+        *st = v;
     }
 }
 

@@ -12,7 +12,7 @@ __global__ __launch_bounds__(64) void k_decompress(const uint8_t* __restrict__ s
                                                    uint32_t* d_err)
 {
     __shared__ float tile[kTileFloats];
-    decompress_chunk<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
+    decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v)

@@ -25,7 +25,11 @@ __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, 
     if (w0 != kMagic) return 6;                                     // FZ_ERR_STREAM
     if (w1 != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16))) return 7;  // FZ_ERR_VERSION
     if (*reinterpret_cast<const uint32_t*>(s + kOffStatus) != 0u) return 8;    // FZ_ERR_STATUS
-    if (s[kOffDtype] != 0 || s[kOffRank] != rank) return 6;
+    if (s[kOffDtype] != 0 || s[kOffRank] != rank || s[kOffEbMode] > 2) return 6;
+    if (s[kOffEbMode] == 2) {  // the point-wise mode's step: an integer in [2, 2^24)
+        const float st = *reinterpret_cast<const float*>(s + kOffEbx2);
+        if (!(st >= 2.0f && st < 16777216.0f) || st != __builtin_floorf(st)) return 6;
+    }
     for (int i = 0; i < 3; i++)
         if (reinterpret_cast<const uint64_t*>(s + kOffDims)[i] != (uint64_t)g.n[i]) return 6;
     if (*reinterpret_cast<const uint32_t*>(s + kOffNChunks) != (uint32_t)g.n_chunks) return 6;
@@ -78,26 +82,37 @@ __device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], uint3
     return bad;
 }
 
-template <int CNT, bool VEC4>
-__device__ __forceinline__ void store_run(float* __restrict__ p, const int* q, float ebx2)
+// Dequantization (Sec. 2.3): q * 2eb in fp32, or in the point-wise relative
+// mode the inverse of the bit-pattern transform with the stream's step.
+template <bool PW>
+__device__ __forceinline__ float dequant(int q, float ebx2, uint32_t step)
+{
+    if constexpr (PW) return pw_dequant(q, step);
+    else return (float)q * ebx2;
+}
+
+template <int CNT, bool VEC4, bool PW>
+__device__ __forceinline__ void store_run(float* __restrict__ p, const int* q, float ebx2, uint32_t step)
 {
     if (VEC4) {
 #pragma unroll
         for (int j = 0; j < CNT / 4; j++)
-            *reinterpret_cast<float4*>(p + 4 * j) = make_float4((float)q[4 * j] * ebx2, (float)q[4 * j + 1] * ebx2,
-                                                                (float)q[4 * j + 2] * ebx2, (float)q[4 * j + 3] * ebx2);
+            *reinterpret_cast<float4*>(p + 4 * j) =
+                make_float4(dequant<PW>(q[4 * j], ebx2, step), dequant<PW>(q[4 * j + 1], ebx2, step),
+                            dequant<PW>(q[4 * j + 2], ebx2, step), dequant<PW>(q[4 * j + 3], ebx2, step));
     } else {
 #pragma unroll
-        for (int j = 0; j < CNT; j++) p[j] = (float)q[j] * ebx2;
+        for (int j = 0; j < CNT; j++) p[j] = dequant<PW>(q[j], ebx2, step);
     }
 }
 
-template <int CNT>
-__device__ __forceinline__ void store_run_masked(float* __restrict__ p, const int* q, float ebx2, int valid)
+template <int CNT, bool PW>
+__device__ __forceinline__ void store_run_masked(float* __restrict__ p, const int* q, float ebx2, uint32_t step,
+                                                 int valid)
 {
 #pragma unroll
     for (int j = 0; j < CNT; j++)
-        if (j < valid) p[j] = (float)q[j] * ebx2;
+        if (j < valid) p[j] = dequant<PW>(q[j], ebx2, step);
 }
 
 // Decompress chunk c of a field with one wave (lane = 0..63; the workgroup is
@@ -108,7 +123,7 @@ __device__ __forceinline__ void store_run_masked(float* __restrict__ p, const in
 constexpr int kTilePitch = 68;
 constexpr int kTileFloats = 32 * kTilePitch;
 
-template <int RANK, bool VEC4>
+template <int RANK, bool VEC4, bool PW>
 __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, float* __restrict__ y, const Geom& g,
                                                  uint32_t* d_err, int64_t c, int lane, float* tile)
 {
@@ -118,6 +133,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
         return;
     }
     const float ebx2 = *reinterpret_cast<const float*>(s + kOffEbx2);
+    const uint32_t step = PW ? (uint32_t)ebx2 : 0u;  // the point-wise mode's step (checked by check_header)
     const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
     const uint64_t payload_units = (total - g.payload_off) / 16;
     const uint32_t* tab = reinterpret_cast<const uint32_t*>(s + g.table_off + 8 * c);
@@ -250,7 +266,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     const int ey = clampi(ext[1] - 4 * py, 0, 4), ex = clampi(ext[2] - 8 * px, 0, 8);
 #pragma unroll
                     for (int r = 0; r < 4; r++)
-                        if (r < ey) store_run_masked<8>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, ex);
+                        if (r < ey) store_run_masked<8, PW>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, step, ex);
                 } else if (VEC4) {
                     // the plane goes through LDS so that every store instruction
                     // writes 4 whole rows of 64 values (a lane's own 4x8 patch
@@ -258,10 +274,12 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         float* t = tile + (4 * py + r) * kTilePitch + 8 * px;
-                        *reinterpret_cast<float4*>(t) = make_float4((float)d[8 * r] * ebx2, (float)d[8 * r + 1] * ebx2,
-                                                                    (float)d[8 * r + 2] * ebx2, (float)d[8 * r + 3] * ebx2);
-                        *reinterpret_cast<float4*>(t + 4) = make_float4((float)d[8 * r + 4] * ebx2, (float)d[8 * r + 5] * ebx2,
-                                                                        (float)d[8 * r + 6] * ebx2, (float)d[8 * r + 7] * ebx2);
+                        *reinterpret_cast<float4*>(t) =
+                            make_float4(dequant<PW>(d[8 * r], ebx2, step), dequant<PW>(d[8 * r + 1], ebx2, step),
+                                        dequant<PW>(d[8 * r + 2], ebx2, step), dequant<PW>(d[8 * r + 3], ebx2, step));
+                        *reinterpret_cast<float4*>(t + 4) =
+                            make_float4(dequant<PW>(d[8 * r + 4], ebx2, step), dequant<PW>(d[8 * r + 5], ebx2, step),
+                                        dequant<PW>(d[8 * r + 6], ebx2, step), dequant<PW>(d[8 * r + 7], ebx2, step));
                     }
                     __syncthreads();  // one wave: orders the tile's writes before its reads
                     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -279,7 +297,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     __syncthreads();  // the tile is rewritten by the next step
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; r++) store_run<8, VEC4>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2);
+                    for (int r = 0; r < 4; r++) store_run<8, VEC4, PW>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, step);
                 }
             } else if (RANK == 2) {
 #pragma unroll
@@ -302,11 +320,11 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                 const int64_t yy = org[0] + 2 * st, x0 = org[1] + 16 * lane;
                 if (edge) {
                     const int ex = clampi(ext[1] - 16 * lane, 0, 16);
-                    store_run_masked<16>(y + (yy * g.n[1] + x0), d, ebx2, ex);
-                    if (2 * st + 1 < ext[0]) store_run_masked<16>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, ex);
+                    store_run_masked<16, PW>(y + (yy * g.n[1] + x0), d, ebx2, step, ex);
+                    if (2 * st + 1 < ext[0]) store_run_masked<16, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step, ex);
                 } else {
-                    store_run<16, VEC4>(y + (yy * g.n[1] + x0), d, ebx2);
-                    store_run<16, VEC4>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2);
+                    store_run<16, VEC4, PW>(y + (yy * g.n[1] + x0), d, ebx2, step);
+                    store_run<16, VEC4, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step);
                 }
             } else {
 #pragma unroll
@@ -319,9 +337,9 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                 const int64_t x0 = org[0] + (int64_t)kStepCodes * st + kPatchCodes * lane;
                 if (edge) {
                     const int valid = clampi(ext[0] - ((int64_t)kStepCodes * st + kPatchCodes * lane), 0, 32);
-                    store_run_masked<32>(y + x0, d, ebx2, valid);
+                    store_run_masked<32, PW>(y + x0, d, ebx2, step, valid);
                 } else {
-                    store_run<32, VEC4>(y + x0, d, ebx2);
+                    store_run<32, VEC4, PW>(y + x0, d, ebx2, step);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -330,6 +348,16 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     if (nout && (esc_bad || seen != nout)) {
         if (lane == 0 && d_err) atomicCAS(d_err, 0u, 6u);
     }
+}
+
+// Decompress chunk c with the stream's quantizer (the mode byte is uniform:
+// one of the two bodies runs).
+template <int RANK, bool VEC4>
+__device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, float* __restrict__ y,
+                                                     const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
+{
+    if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true>(s, y, g, d_err, c, lane, tile);
+    else decompress_chunk<RANK, VEC4, false>(s, y, g, d_err, c, lane, tile);
 }
 
 }  // namespace fz

@@ -96,6 +96,57 @@ __device__ __forceinline__ int prequant(float v, float inv, uint32_t& acc)
 
 __device__ __forceinline__ uint32_t absu(int d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
 
+// The quantizer a stream records.  step == 0: the 2eb grid of the ABS and REL
+// modes, q = rint(x * inv).  step > 0: the point-wise relative mode, where
+// the data's logarithmic transform is the float's bit pattern b (exponent and
+// mantissa, a piecewise-linear log2 exact in integers) and q = sign(x) *
+// floor((b + floor(step / 2)) / step).  inv is 0 in that mode, so x * inv
+// flags exactly the non-finite inputs.
+struct Quant {
+    float inv;
+    uint32_t step;
+    uint32_t magic;  // floor(2^32 / step): the division by step as a multiply-high
+};
+
+__device__ __forceinline__ Quant quant_of(const uint8_t* hdr)
+{
+    Quant z;
+    z.inv = *reinterpret_cast<const float*>(hdr + kOffInv);
+    const bool pw = hdr[kOffEbMode] == 2;
+    z.step = pw ? (uint32_t)*reinterpret_cast<const float*>(hdr + kOffEbx2) : 0u;
+    z.magic = pw ? (uint32_t)(0x100000000ull / (uint64_t)z.step) : 0u;
+    return z;
+}
+
+// q of the point-wise relative mode.  n < 2^32, so the multiply-high estimate
+// is floor(n / step) or one less, and one compare corrects it (Granlund and
+// Montgomery's division by an invariant integer).
+__device__ __forceinline__ int pw_quant(float x, const Quant& z)
+{
+    const uint32_t bits = __float_as_uint(x);
+    const uint32_t n = (bits & 0x7FFFFFFFu) + (z.step >> 1);
+    uint32_t a = __umulhi(n, z.magic);
+    a += (n - a * z.step >= z.step) ? 1u : 0u;
+    return (bits >> 31) ? -(int)a : (int)a;
+}
+
+// its inverse: the float with the sign of q and the bits min(|q| * step, the
+// largest finite float)
+__device__ __forceinline__ float pw_dequant(int q, uint32_t step)
+{
+    const uint64_t m = (uint64_t)absu(q) * step;
+    const uint32_t b = m > 0x7F7FFFFFull ? 0x7F7FFFFFu : (uint32_t)m;
+    return __uint_as_float(b | (q < 0 ? 0x80000000u : 0u));
+}
+
+// one value through the stream's quantizer; acc flags NaN/Inf (and in the
+// grid modes |x * inv| >= 2^31)
+__device__ __forceinline__ int prequant(float v, const Quant& z, uint32_t& acc)
+{
+    const int q = prequant(v, z.inv, acc);
+    return z.step ? pw_quant(v, z) : q;
+}
+
 typedef short fz_short2 __attribute__((ext_vector_type(2)));
 
 // Sign-magnitude 16-bit codes of d[i] and d[i+16] packed into one word

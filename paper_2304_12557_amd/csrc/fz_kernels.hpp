@@ -10,7 +10,8 @@ struct HeaderImage {
     uint32_t w[kHeaderBytes / 4];
 };
 
-hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, bool rel, double eb,
+// mode: FZ_EB_ABS, FZ_EB_REL (adds the range pass) or FZ_EB_PWREL
+hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
                            hipStream_t st);
 hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);
 
@@ -20,5 +21,10 @@ int64_t minmax_blocks(int64_t n);
 HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float inv);
 // eb parameters of an absolute bound; false if unusable
 bool abs_params(double eb, float* ebx2, float* inv);
+// the header's quantizer fields for a bound and mode, as far as the host
+// knows them (REL: derived on the device, 0 here; PWREL: ebx2 holds the step
+// S = floor(eb * 2^24 / (1 + eb)), inv 0).  Returns FZ_OK, FZ_ERR_ARG (eb not
+// finite and > 0, unknown mode) or FZ_ERR_EB_RANGE (unusable bound).
+int bound_params(double eb, int mode, float* ebx2, float* inv);
 
 }  // namespace fz

@@ -184,3 +184,19 @@ def batch_field(shape, seed):
 def rel_eb_choice(seed):
     rng = np.random.default_rng(seed)
     return [1e-2, 1e-3, 1e-4][int(rng.integers(0, 3))]
+
+
+def wide_field(shape, seed):
+    """Values spanning several binades (smooth in log2), a few negative
+    regions, and sparse zeros, fp32 denormals and values near 1e30: the
+    workload of the point-wise relative mode."""
+    rng = np.random.default_rng(seed)
+    mag = np.exp(sine_field(shape, seed=seed).astype(np.float64) * 0.5)
+    sign = np.where(sine_field(shape, seed=seed + 1) > 3.5, -1.0, 1.0)
+    x = (mag * sign).astype(np.float32)
+    flat = x.reshape(-1)
+    # each special value costs up to 8 escaped deltas; a layer holds at most 256
+    flat[::1009] = 0.0
+    flat[7::2111] = np.float32(3e-42)
+    flat[5::3001] = rng.standard_normal(flat[5::3001].size).astype(np.float32) * np.float32(1e30)
+    return x

@@ -46,6 +46,10 @@ def test_argument_errors_return_immediately():
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), float("nan"), 1, ctypes.c_void_p(16), None) == 1
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 7, ctypes.c_void_p(16), None) == 1
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-45, 0, ctypes.c_void_p(16), None) == 4
+    # point-wise relative mode: a step S = floor(eps 2^24 / (1 + eps)) below 2 is out of range
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-8, 2, ctypes.c_void_p(16), None) == 4
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1.1e-7, 2, ctypes.c_void_p(16), None) == 4
+    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 3, ctypes.c_void_p(16), None) == 1
     bad = fz.FzDims()
     bad.rank = 4
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(bad), 1e-3, 1, ctypes.c_void_p(16), None) == 1

@@ -115,6 +115,21 @@ def test_status_bits_match_oracle():
     assert fz.stream_info(buf)["status"] == st == O.ERR_OUTLIER_CAP
 
 
+def test_status_precedence():
+    """NaN / Inf or an overflowing x/(2eb) end the pipeline at
+    prequantization: the escape-cap bit, which the rest of the field alone
+    would set, is not reported with them."""
+    rng = np.random.default_rng(4)
+    w = (rng.standard_normal((20, 40, 70)) * 1e6).astype(np.float32)
+    for v, eb, want in ((np.nan, 0.5, O.ERR_NONFINITE), (np.inf, 0.5, O.ERR_NONFINITE),
+                        (np.float32(3e38), 0.5, O.ERR_EB_RANGE)):
+        bad = w.copy()
+        bad[19, 39, 69] = v
+        _, st = O.compress(bad, eb, O.EB_ABS)
+        buf, _ = gpu_compress(bad, eb, O.EB_ABS)
+        assert fz.stream_info(buf)["status"] == st == want
+
+
 @pytest.mark.parametrize("where", ["first", "last", "tail", "middle"])
 @pytest.mark.parametrize("val", [np.inf, -np.inf, np.nan])
 def test_rel_range_nonfinite(where, val):

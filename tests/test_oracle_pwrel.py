@@ -75,23 +75,10 @@ def test_quantization_brute_force(step):
         assert abs(m - int(bits[i])) <= step // 2 + (1 if m == 0x7F7FFFFF else 0) or m == 0x7F7FFFFF
 
 
-def wide_field(shape, seed):
-    rng = np.random.default_rng(seed)
-    mag = np.exp(synth.sine_field(shape, seed=seed).astype(np.float64) * 0.5)  # smooth in log2, several binades
-    sign = np.where(synth.sine_field(shape, seed=seed + 1) > 3.5, -1.0, 1.0)  # a few negative regions
-    x = (mag * sign).astype(np.float32)
-    flat = x.reshape(-1)
-    # sparse special values (each costs up to 8 escaped deltas; a layer holds at most 256)
-    flat[::1009] = 0.0
-    flat[7::2111] = np.float32(3e-42)  # denormals
-    flat[5::3001] = rng.standard_normal(flat[5::3001].size).astype(np.float32) * np.float32(1e30)
-    return x
-
-
 @pytest.mark.parametrize("shape,eps", [((20, 40, 70), 1e-3), ((45, 1030), 1e-2), ((70001,), 1e-4),
                                        ((16, 32, 64), 0.3)])
 def test_round_trip_point_wise_bound(shape, eps):
-    x = wide_field(shape, seed=sum(shape))
+    x = synth.wide_field(shape, seed=sum(shape))
     s, st = O.compress(x, eps, O.EB_PWREL)
     assert st == 0
     y, err = O.decompress(s, shape)
