@@ -369,6 +369,7 @@ def bench_serving(n_requests, max_seconds, n_pool=48, seed=4000):
 # share when 4 GPUs move data at once)
 REL_EBS = (1e-2, 5e-3, 1e-3, 5e-4, 1e-4)
 PAPER_LINKS_GBPS = (32.0, 11.4)
+PW_EPS = (1e-2, 1e-3, 1e-4)  # point-wise relative bounds of the extra mode
 
 
 def rate_distortion(xt, shape):
@@ -392,6 +393,47 @@ def rate_distortion(xt, shape):
         rows.append({"eb": eb, "ratio": round(ratio, 3), "bitrate": round(32.0 / ratio, 4),
                      "psnr_db": round(q["psnr"], 3), "max_abs_err": q["max_abs_err"],
                      "max_err_over_eb": round(q["max_abs_err"] / eb_abs, 6)})
+    return rows
+
+
+def pointwise_relative(xt, shape, stream, reps):
+    """The point-wise relative mode on the same field: compress and
+    decompress time (HIP events), ratio, and the largest |x' - x| /
+    max(|x|, 2^-126) seen (the mode's bound is eps)."""
+    import numpy as np
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    buf = torch.empty(fz.compress_bound(shape), dtype=torch.uint8, device=xt.device)
+    y = torch.empty_like(xt)
+    in_bytes = 4 * xt.numel()
+    rows = []
+    for eps in PW_EPS:
+        fz.compress(xt, eps, "pwrel", out=buf)
+        fz.decompress(buf, shape, out=y)
+        torch.cuda.synchronize()
+        info = fz.stream_info(buf)
+        if info["status"]:
+            rows.append({"eps": eps, "status": int(info["status"])})
+            continue
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        for k in range(reps):
+            ev[k][0].record(stream)
+            fz.compress(xt, eps, "pwrel", out=buf)
+            ev[k][1].record(stream)
+            fz.decompress(buf, shape, out=y)
+            ev[k][2].record(stream)
+        torch.cuda.synchronize()
+        tc = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        td = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        xd = xt.double()
+        rel = ((y.double() - xd).abs() / xd.abs().clamp_min(2.0 ** -126)).max().item()
+        del xd
+        rows.append({"eps": eps, "ratio": round(in_bytes / int(info["total_bytes"]), 3),
+                     "compress_GBps": round(in_bytes / 1e9 / (tc * 1e-3), 2),
+                     "decompress_GBps": round(in_bytes / 1e9 / (td * 1e-3), 2),
+                     "max_pointwise_rel_err": rel, "step": int(info["ebx2"])})
     return rows
 
 
@@ -583,6 +625,7 @@ def main():
         out["rate_distortion"] = rate_distortion(xt, shape)
         out["overall_throughput"] = overall_throughput(xt, shape, a.eb, s_bytes, in_bytes / 1e9 / (tc * 1e-3),
                                                        a.steps)
+        out["pointwise_relative"] = pointwise_relative(xt, shape, stream, a.steps)
     if not a.no_ablation:
         out["ablation"] = bench_ablation(xt, float(info["inv"]), tca)
     if not a.no_layers:

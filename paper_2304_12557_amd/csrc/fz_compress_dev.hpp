@@ -700,7 +700,7 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
     // used when every value is finite, and a NaN or an infinity shows up in
     // the result (the minimum is -Inf or NaN, or the maximum +Inf or NaN)
     float fmn = __builtin_inff(), fmx = -__builtin_inff();
-    auto take4 = [&](const float4& v) {
+    auto take4 = [&](const fz_f32x4& v) {
         fmn = __builtin_elementwise_minimum(__builtin_elementwise_minimum(fmn, v.x), v.y);
         fmx = __builtin_elementwise_maximum(__builtin_elementwise_maximum(fmx, v.x), v.y);
         fmn = __builtin_elementwise_minimum(__builtin_elementwise_minimum(fmn, v.z), v.w);
@@ -710,11 +710,12 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
     const int64_t tid = blk * 256 + threadIdx.x;
     const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     const int64_t n4 = vec ? n / 4 : 0;
-    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const fz_f32x4* x4 = reinterpret_cast<const fz_f32x4*>(x);
     // backwards, so that the front of the field, which the compression
     // kernel reads first, is the most recently read (one load per
-    // iteration: unrolling by strided loads measured slower)
-    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) take4(x4[i]);
+    // iteration: unrolling by strided loads measured slower); streaming
+    // loads, as no value is read twice here
+    for (int64_t i = n4 - 1 - tid; i >= 0; i -= stride) take4(__builtin_nontemporal_load(x4 + i));
     for (int64_t k = 4 * n4 + tid; k < n; k += stride) {
         fmn = __builtin_elementwise_minimum(fmn, x[k]);
         fmx = __builtin_elementwise_maximum(fmx, x[k]);

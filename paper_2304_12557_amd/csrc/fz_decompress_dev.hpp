@@ -119,9 +119,32 @@ __device__ __forceinline__ void store_run_masked(float* __restrict__ p, const in
 // that one wave).  `tile` is kTileFloats of LDS.  A stream that fails a check
 // writes an fz_status code to *d_err (if given) and leaves the chunk's output
 // untouched.
-// LDS tile of one 3-D step (32 rows of 64 values, padded against bank conflicts)
+// LDS tile of one step: 3-D, 32 rows of 64 values with a row pitch of 68;
+// 2-D and 1-D, the step's 2048 values in order with 4 floats of padding after
+// every 32 (both paddings spread a wave's 16-byte accesses over the banks)
 constexpr int kTilePitch = 68;
-constexpr int kTileFloats = 32 * kTilePitch;
+constexpr int kTileFloats = 2048 + 4 * (2048 / 32);
+static_assert(32 * kTilePitch <= kTileFloats, "the 3-D tile fits");
+__device__ __forceinline__ int run_slot(int i) { return i + 4 * (i >> 5); }
+
+// Store one 2-D or 1-D step from its LDS tile (filled by the caller):
+// instruction i writes values 256 i .. 256 i + 255 of the step, a run of 1 KiB
+// of whole lines, streamed out.  Values 1024 r .. 1024 r + 1023 start at byte
+// r * row_bytes from `base`: the step's second row in 2-D, 4096 in 1-D (one
+// contiguous run).
+__device__ __forceinline__ void store_tile_runs(const float* tile, float* base, uint32_t row_bytes, int lane)
+{
+    __syncthreads();  // one wave: orders the tile's writes before its reads
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, -1, kBufferFlags);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const float4 v = *reinterpret_cast<const float4*>(tile + run_slot(256 * i + 4 * lane));
+        const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+        const uint32_t soff = (uint32_t)(i >> 2) * row_bytes + 1024u * (uint32_t)(i & 3);
+        __builtin_amdgcn_raw_buffer_store_b128(w, rs, 16u * (uint32_t)lane, soff, kCacheStream);
+    }
+    __syncthreads();  // the tile is rewritten by the next step
+}
 
 template <int RANK, bool VEC4, bool PW>
 __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, float* __restrict__ y, const Geom& g,
@@ -292,7 +315,8 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                                                           4 * (lane & 15));
                         const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
                                             __float_as_uint(v.w)};
-                        __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2], 0);
+                        __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2],
+                                                               kCacheStream);
                     }
                     __syncthreads();  // the tile is rewritten by the next step
                 } else {
@@ -322,6 +346,19 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     const int ex = clampi(ext[1] - 16 * lane, 0, 16);
                     store_run_masked<16, PW>(y + (yy * g.n[1] + x0), d, ebx2, step, ex);
                     if (2 * st + 1 < ext[0]) store_run_masked<16, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step, ex);
+                } else if (VEC4) {
+                    // through LDS, so that every store writes 1 KiB of one row
+#pragma unroll
+                    for (int r = 0; r < 2; r++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            const int* q = d + 16 * r + 4 * j;
+                            *reinterpret_cast<float4*>(tile + run_slot(1024 * r + 16 * lane + 4 * j)) =
+                                make_float4(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step),
+                                            dequant<PW>(q[2], ebx2, step), dequant<PW>(q[3], ebx2, step));
+                        }
+                    // row offsets stay below 2^32: the contiguous extent is below 2^25
+                    store_tile_runs(tile, y + (yy * g.n[1] + org[1]), 4u * (uint32_t)g.n[1], lane);
                 } else {
                     store_run<16, VEC4, PW>(y + (yy * g.n[1] + x0), d, ebx2, step);
                     store_run<16, VEC4, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step);
@@ -338,6 +375,15 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                 if (edge) {
                     const int valid = clampi(ext[0] - ((int64_t)kStepCodes * st + kPatchCodes * lane), 0, 32);
                     store_run_masked<32, PW>(y + x0, d, ebx2, step, valid);
+                } else if (VEC4) {
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        const int* q = d + 4 * j;
+                        *reinterpret_cast<float4*>(tile + run_slot(32 * lane + 4 * j)) =
+                            make_float4(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step),
+                                        dequant<PW>(q[2], ebx2, step), dequant<PW>(q[3], ebx2, step));
+                    }
+                    store_tile_runs(tile, y + (org[0] + (int64_t)kStepCodes * st), 4096u, lane);
                 } else {
                     store_run<32, VEC4, PW>(y + x0, d, ebx2, step);
                 }
