@@ -396,6 +396,17 @@ static void encode_chunk(const geom_t *g, const int32_t *q, int64_t c, chunk_out
  * flags (512 B per chunk) | payload.  Chunk offsets are the exclusive
  * prefix sum of units_c = nnz_c + ceil(out_c / 2) (Sec. 3.4 computes block
  * offsets with a prefix sum).                                             */
+/* the header fields that depend on the input type and the bound */
+typedef struct {
+    int dtype, eb_mode;
+    double eb;
+    float ebx2, inv, vmin, vmax;
+    double ebx2_64, inv_64; /* fp64 input only (bytes 104 and 112; 0 otherwise) */
+} hdr_t;
+
+static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const hdr_t *h, uint8_t *out,
+                           int64_t cap, uint32_t *status_out, int threads);
+
 int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, int eb_mode,
                      uint8_t *out, int64_t cap, uint32_t *status_out, int threads)
 {
@@ -404,16 +415,108 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
     if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != FZO_EB_ABS && eb_mode != FZO_EB_REL && eb_mode != FZO_EB_PWREL))
         return -1;
     int64_t N = g.n[0] * g.n[1] * g.n[2];
-    int64_t H = header_bytes(&g);
-    if (cap < H) return -1;
+    if (cap < header_bytes(&g)) return -1;
 
-    float ebx2, inv, vmin, vmax;
-    uint32_t status = (uint32_t)fzo_eb_params(x, N, eb, eb_mode, &ebx2, &inv, &vmin, &vmax);
+    hdr_t h;
+    memset(&h, 0, sizeof(h));
+    h.dtype = 0;
+    h.eb_mode = eb_mode;
+    h.eb = eb;
+    uint32_t status = (uint32_t)fzo_eb_params(x, N, eb, eb_mode, &h.ebx2, &h.inv, &h.vmin, &h.vmax);
     int32_t *q = (int32_t *)calloc((size_t)N, sizeof(int32_t));
     if (!status)
-        status |= (uint32_t)(eb_mode == FZO_EB_PWREL ? fzo_prequant_pw(x, N, (uint32_t)ebx2, q)
-                                                     : fzo_prequant(x, N, inv, q));
+        status |= (uint32_t)(eb_mode == FZO_EB_PWREL ? fzo_prequant_pw(x, N, (uint32_t)h.ebx2, q)
+                                                     : fzo_prequant(x, N, h.inv, q));
+    int64_t r = emit_stream(&g, q, status, &h, out, cap, status_out, threads);
+    free(q);
+    return r;
+}
 
+/* ------------------------------------------------ O1d/O2d: fp64 input
+ * The same quantizer in double precision (the method is stated for real
+ * values; fp64 is the input type of the HACC-like workloads, Sec. 4.1).
+ * ABS: eb_abs = eb; REL: eb_abs = eb * (vmax - vmin) over the double values
+ * (-0 counts as +0; a constant field uses eb * |vmax|, or eb if that is 0).
+ * ebx2 = 2 eb_abs and inv = 1 / ebx2 in double; valid when ebx2 is a normal
+ * double and inv is finite.  q = (int32) rint(x * inv) with one double
+ * multiply and round-half-even, for finite x with |x * inv| < 2^31;
+ * x' = (double) q * ebx2.  Both doubles are recorded in the header (bytes
+ * 104 and 112); the fp32 slots hold their fp32 roundings for information. */
+int fzo_eb_params_f64(const double *x, int64_t n, double eb, int eb_mode, double *ebx2, double *inv,
+                      double *vmin, double *vmax)
+{
+    double lo = 0.0, hi = 0.0;
+    int status = 0, seen = 0;
+    *ebx2 = 0.0; *inv = 0.0;
+    for (int64_t i = 0; i < (eb_mode == FZO_EB_REL ? n : 0); i++) {
+        if (!isfinite(x[i])) { status |= FZO_ERR_NONFINITE; continue; }
+        double v = x[i] == 0.0 ? 0.0 : x[i];
+        if (!seen || v < lo) lo = v;
+        if (!seen || v > hi) hi = v;
+        seen = 1;
+    }
+    *vmin = lo; *vmax = hi;
+    if (status) return status;
+    double eb_abs = eb;
+    if (eb_mode == FZO_EB_REL) {
+        double range = hi - lo;
+        if (range > 0.0) eb_abs = eb * range;
+        else eb_abs = eb * (fabs(hi) > 0.0 ? fabs(hi) : 1.0);
+    }
+    double e2 = 2.0 * eb_abs, iv = 1.0 / e2;
+    if (!(e2 >= DBL_MIN) || !isfinite(e2) || !isfinite(iv) || !(iv > 0.0)) return FZO_ERR_EB_RANGE;
+    *ebx2 = e2; *inv = iv;
+    return 0;
+}
+
+int fzo_prequant_f64(const double *x, int64_t n, double inv, int32_t *q)
+{
+    int status = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double v = x[i];
+        if (!isfinite(v)) { status |= FZO_ERR_NONFINITE; q[i] = 0; continue; }
+        double p = v * inv;
+        if (!(fabs(p) < 2147483648.0)) { status |= FZO_ERR_EB_RANGE; q[i] = 0; continue; }
+        q[i] = (int32_t)rint(p);
+    }
+    return status;
+}
+
+int64_t fzo_compress_f64(const double *x, int rank, const int64_t *dims, double eb, int eb_mode,
+                         uint8_t *out, int64_t cap, uint32_t *status_out, int threads)
+{
+    geom_t g;
+    if (make_geom(rank, dims, &g)) return -1;
+    if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != FZO_EB_ABS && eb_mode != FZO_EB_REL)) return -1;
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    if (cap < header_bytes(&g)) return -1;
+
+    hdr_t h;
+    memset(&h, 0, sizeof(h));
+    h.dtype = 1;
+    h.eb_mode = eb_mode;
+    h.eb = eb;
+    double lo, hi;
+    uint32_t status = (uint32_t)fzo_eb_params_f64(x, N, eb, eb_mode, &h.ebx2_64, &h.inv_64, &lo, &hi);
+    h.ebx2 = (float)h.ebx2_64;
+    h.inv = (float)h.inv_64;
+    h.vmin = (float)lo;
+    h.vmax = (float)hi;
+    int32_t *q = (int32_t *)calloc((size_t)N, sizeof(int32_t));
+    if (!status) status |= (uint32_t)fzo_prequant_f64(x, N, h.inv_64, q);
+    int64_t r = emit_stream(&g, q, status, &h, out, cap, status_out, threads);
+    free(q);
+    return r;
+}
+
+/* O4-O8 and the header: encode the chunks of q (unless status is set) and
+ * write the stream. */
+static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const hdr_t *h, uint8_t *out,
+                           int64_t cap, uint32_t *status_out, int threads)
+{
+    const geom_t g = *g0;
+    const int rank = g.rank;
+    int64_t H = header_bytes(&g);
     chunk_out_t *co = (chunk_out_t *)calloc((size_t)g.n_chunks, sizeof(chunk_out_t));
     if (!status) {
 #ifdef _OPENMP
@@ -464,27 +567,30 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
     int overflow = status == 0xffffffffu;
     for (int64_t c = 0; c < g.n_chunks; c++) { free(co[c].bricks); free(co[c].oidx); free(co[c].oval); }
     free(co);
-    free(q);
 
     /* header (F1) */
     put32(out + 0, FZO_MAGIC);
     put16(out + 4, FZO_VERSION);
     put16(out + 6, FZO_HEADER_BYTES);
     put32(out + 8, status);
-    out[12] = 0; /* dtype f32 */
+    out[12] = (uint8_t)h->dtype; /* 0 f32, 1 f64 */
     out[13] = (uint8_t)rank;
-    out[14] = (uint8_t)eb_mode;
+    out[14] = (uint8_t)h->eb_mode;
     for (int i = 0; i < 3; i++) put64(out + 16 + 8 * i, (uint64_t)g.n[i]);
-    memcpy(out + 40, &eb, 8);
-    memcpy(out + 48, &ebx2, 4);
-    memcpy(out + 52, &inv, 4);
-    memcpy(out + 56, &vmin, 4);
-    memcpy(out + 60, &vmax, 4);
+    memcpy(out + 40, &h->eb, 8);
+    memcpy(out + 48, &h->ebx2, 4);
+    memcpy(out + 52, &h->inv, 4);
+    memcpy(out + 56, &h->vmin, 4);
+    memcpy(out + 60, &h->vmax, 4);
     for (int i = 0; i < 3; i++) put16(out + 64 + 2 * i, (uint16_t)g.box[i]);
     put32(out + 72, (uint32_t)g.n_chunks);
     put64(out + 80, nnz_total);
     put64(out + 88, nout_total);
     put64(out + 96, (uint64_t)total);
+    if (h->dtype == 1) {
+        memcpy(out + 104, &h->ebx2_64, 8);
+        memcpy(out + 112, &h->inv_64, 8);
+    }
     if (status_out) *status_out = status;
     return overflow ? -2 : total;
 }
@@ -495,7 +601,20 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
  * inverse Lorenzo = inclusive prefix sums along x, then y, then z inside the
  * chunk box (mod 2^32), D6 x' = fp32((float)q * ebx2), or in PWREL mode the
  * inverse transform of q * S (O2b).                                       */
+static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims);
+
 int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims)
+{
+    return decompress_any(s, size, x, NULL, rank, dims);
+}
+
+/* fp64 streams (dtype 1): x' = (double) q * ebx2, ebx2 the double at byte 104 */
+int fzo_decompress_f64(const uint8_t *s, int64_t size, double *x, int rank, const int64_t *dims)
+{
+    return decompress_any(s, size, NULL, x, rank, dims);
+}
+
+static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims)
 {
     geom_t g;
     if (make_geom(rank, dims, &g)) return FZO_DERR_ARG;
@@ -503,7 +622,7 @@ int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int
     if (get32(s) != FZO_MAGIC) return FZO_DERR_STREAM;
     if (get16(s + 4) != FZO_VERSION || get16(s + 6) != FZO_HEADER_BYTES) return FZO_DERR_VERSION;
     if (get32(s + 8) != 0) return FZO_DERR_STATUS;
-    if (s[12] != 0 || s[13] != rank) return FZO_DERR_STREAM;
+    if (s[12] != (x64 ? 1 : 0) || s[13] != rank) return FZO_DERR_STREAM;
     for (int i = 0; i < 3; i++)
         if ((int64_t)get64(s + 16 + 8 * i) != g.n[i]) return FZO_DERR_STREAM;
     if ((int64_t)get32(s + 72) != g.n_chunks) return FZO_DERR_STREAM;
@@ -515,7 +634,12 @@ int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int
     /* the bound mode: 0 ABS, 1 REL (x' = q * ebx2), 2 PWREL (x' from the
      * transformed value q * S, S recorded in the ebx2 slot) */
     int mode = s[14];
-    if (mode > FZO_EB_PWREL) return FZO_DERR_STREAM;
+    if (mode > FZO_EB_PWREL || (x64 && mode == FZO_EB_PWREL)) return FZO_DERR_STREAM;
+    double ebx2_64 = 0.0;
+    if (x64) {
+        memcpy(&ebx2_64, s + 104, 8);
+        if (!(ebx2_64 >= DBL_MIN) || !isfinite(ebx2_64)) return FZO_DERR_STREAM;
+    }
     uint32_t step = 0;
     if (mode == FZO_EB_PWREL) {
         if (!(ebx2 >= 2.0f && ebx2 < 16777216.0f) || ebx2 != floorf(ebx2)) return FZO_DERR_STREAM;
@@ -597,7 +721,8 @@ int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int
         for (int64_t a = 0; a < e0; a++)
             for (int64_t b = 0; b < e1; b++)
                 for (int64_t cc = 0; cc < e2; cc++)
-                    x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] =
+                    if (x64) x64[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = (double)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2_64;
+                    else x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] =
                         mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)box[(a * e1 + b) * e2 + cc], step)
                                              : (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
     }

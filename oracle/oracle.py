@@ -62,6 +62,15 @@ def lib():
         L.fzo_compress.restype = ctypes.c_int64
         L.fzo_decompress.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int, _i64p]
         L.fzo_decompress.restype = ctypes.c_int
+        L.fzo_eb_params_f64.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+        L.fzo_eb_params_f64.restype = ctypes.c_int
+        L.fzo_prequant_f64.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
+        L.fzo_prequant_f64.restype = ctypes.c_int
+        L.fzo_compress_f64.argtypes = [vp, ctypes.c_int, _i64p, ctypes.c_double, ctypes.c_int, vp, ctypes.c_int64,
+                                       vp, ctypes.c_int]
+        L.fzo_compress_f64.restype = ctypes.c_int64
+        L.fzo_decompress_f64.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int, _i64p]
+        L.fzo_decompress_f64.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -161,4 +170,42 @@ def decompress(stream, shape):
     r, d = _dims(shape)
     out = np.zeros(shape, dtype=np.float32)
     err = lib().fzo_decompress(_ptr(s), s.size, _ptr(out), r, d)
+    return out, err
+
+
+def eb_params_f64(x, eb, mode):
+    """fp64 bound parameters: dict(status, ebx2, inv, vmin, vmax), all double."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    o = np.zeros(4, dtype=np.float64)
+    st = lib().fzo_eb_params_f64(_ptr(x), x.size, float(eb), int(mode), _ptr(o[0:1]), _ptr(o[1:2]), _ptr(o[2:3]),
+                                 _ptr(o[3:4]))
+    return {"status": st, "ebx2": float(o[0]), "inv": float(o[1]), "vmin": float(o[2]), "vmax": float(o[3])}
+
+
+def prequant_f64(x, inv):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    q = np.zeros(x.size, dtype=np.int32)
+    st = lib().fzo_prequant_f64(_ptr(x), x.size, float(inv), _ptr(q))
+    return q.reshape(x.shape), st
+
+
+def compress_f64(x, eb, mode=EB_REL, threads=1):
+    """fp64 input: returns (stream bytes as np.uint8, status)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r, d = _dims(x.shape)
+    cap = lib().fzo_bound(r, d)
+    out = np.zeros(cap, dtype=np.uint8)
+    st = np.zeros(1, dtype=np.uint32)
+    n = lib().fzo_compress_f64(_ptr(x), r, d, float(eb), int(mode), _ptr(out), cap, _ptr(st), int(threads))
+    if n < 0:
+        raise ValueError("oracle compress failed: %d" % n)
+    return out[:n].copy(), int(st[0])
+
+
+def decompress_f64(stream, shape):
+    """Returns (float64 array, error code)."""
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    r, d = _dims(shape)
+    out = np.zeros(shape, dtype=np.float64)
+    err = lib().fzo_decompress_f64(_ptr(s), s.size, _ptr(out), r, d)
     return out, err
