@@ -82,6 +82,10 @@ typedef struct {
     uint64_t n_outliers;  /* escaped codes stored as (index, value) pairs */
     uint64_t total_bytes; /* stream size */
     uint64_t header_bytes;/* header + chunk table + flags */
+    uint32_t dtype;       /* input type: 0 fp32, 1 fp64 */
+    uint32_t reserved;
+    double ebx2_f64;      /* fp64 streams: 2 * absolute error bound, in double (0 for fp32) */
+    double inv_f64;       /* fp64 streams: 1 / ebx2_f64 (0 for fp32) */
 } fz_info;
 
 /* status bits written into the header by the device */
@@ -139,6 +143,30 @@ int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, 
  *              is rejected on the device; d_out is then not written
  * Returns FZ_OK once the work is enqueued. */
 int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
+
+/* ------------------------------------------------------------ fp64 input
+ * The same pipeline on fp64 fields (FZ_EB_ABS and FZ_EB_REL): the bound's
+ * parameters, the value range (REL) and the prequantization q = rint(x *
+ * inv) are taken in double (inv = 1 / (2 eb_abs)), so |x' - x| <= eb_abs up
+ * to one double rounding of x * inv and of q * 2eb_abs (the Sec. 2.3
+ * inequality); the integers q then go through the same encoder, and the
+ * stream differs from an fp32 one in the header only: dtype 1 (byte 12),
+ * 2 eb_abs and its reciprocal as doubles at bytes 104 and 112 (their fp32
+ * roundings, and the range's, fill the fp32 slots for information).
+ *
+ * fz_compress_bound_f64: bytes of d_out for fz_compress_f64 -- the fp32
+ * bound, then the integers q (4 B per value) and the range pass's partials.
+ * fz_compress_f64: d_in holds N fp64 values (device); eb_mode FZ_EB_PWREL or
+ * any other value returns FZ_ERR_ARG; in ABS mode a 2 eb below the smallest
+ * normal double returns FZ_ERR_EB_RANGE at once.  Data-dependent errors and
+ * the stream size as for fz_compress.
+ * fz_decompress_f64: d_out receives N fp64 values x' = (double) q * 2eb_abs;
+ * d_err as for fz_decompress (an fp32 stream is FZ_ERR_STREAM here, and an
+ * fp64 stream is FZ_ERR_STREAM for fz_decompress).
+ * The batch and serving layers take fp32 fields only. */
+size_t fz_compress_bound_f64(const fz_dims *dims);
+int fz_compress_f64(const double *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
+int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
 
 /* ------------------------------------------------------------ batches
  * Many fields of uneven rank and size in a fixed, small number of launches

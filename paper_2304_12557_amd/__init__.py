@@ -10,6 +10,7 @@ function here raises; there is no CPU fallback.
     y = decompress(s, x.shape)            # float32 CUDA tensor
 """
 import ctypes
+import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,7 +39,8 @@ class FzInfo(ctypes.Structure):
                 ("ebx2", ctypes.c_float), ("inv", ctypes.c_float), ("vmin", ctypes.c_float),
                 ("vmax", ctypes.c_float), ("n_chunks", ctypes.c_uint32), ("nnz_blocks", ctypes.c_uint64),
                 ("n_outliers", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
-                ("header_bytes", ctypes.c_uint64)]
+                ("header_bytes", ctypes.c_uint64), ("dtype", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("ebx2_f64", ctypes.c_double), ("inv_f64", ctypes.c_double)]
 
 
 class FzCompressJob(ctypes.Structure):
@@ -94,6 +96,12 @@ def lib():
         L.fz_compress.restype = ctypes.c_int
         L.fz_decompress.argtypes = [vp, vp, dp, vp, vp]
         L.fz_decompress.restype = ctypes.c_int
+        L.fz_compress_bound_f64.argtypes = [dp]
+        L.fz_compress_bound_f64.restype = ctypes.c_size_t
+        L.fz_compress_f64.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
+        L.fz_compress_f64.restype = ctypes.c_int
+        L.fz_decompress_f64.argtypes = [vp, vp, dp, vp, vp]
+        L.fz_decompress_f64.restype = ctypes.c_int
         L.fz_stream_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(FzInfo)]
         L.fz_stream_info.restype = ctypes.c_int
         L.fz_strerror.argtypes = [ctypes.c_int]
@@ -141,7 +149,8 @@ SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
-           "fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark", "fz_abl_encode"]
+           "fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark", "fz_abl_encode",
+           "fz_compress_bound_f64", "fz_compress_f64", "fz_decompress_f64"]
 FZ_REQ_COMPRESS = 0
 FZ_REQ_DECOMPRESS = 1
 
@@ -157,8 +166,11 @@ def dims_of(shape):
     return d
 
 
-def compress_bound(shape):
-    return int(lib().fz_compress_bound(ctypes.byref(dims_of(shape))))
+def compress_bound(shape, f64=False):
+    """Output bytes ``compress`` needs for a field of this shape (fp32, or
+    fp64 input with ``f64=True``)."""
+    fn = lib().fz_compress_bound_f64 if f64 else lib().fz_compress_bound
+    return int(fn(ctypes.byref(dims_of(shape))))
 
 
 def header_bytes(shape):
@@ -184,37 +196,48 @@ def _mode(mode):
 
 
 def compress(x, eb, mode="rel", out=None, stream=None):
-    """Compress a float32 CUDA tensor; returns the uint8 output buffer
-    (``compress_bound`` bytes; the stream occupies its first
-    ``stream_size(buf)`` bytes).  Asynchronous on ``stream``."""
+    """Compress a float32 or float64 CUDA tensor; returns the uint8 output
+    buffer (``compress_bound(shape, x.dtype)`` bytes; the stream occupies its
+    first ``stream_size(buf)`` bytes).  Asynchronous on ``stream``."""
     import torch
 
-    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
-        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    if not (x.is_cuda and x.dtype in (torch.float32, torch.float64) and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float32 or float64 CUDA tensor")
+    f64 = x.dtype == torch.float64
     dims = dims_of(x.shape)
-    bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
+    bound = int((lib().fz_compress_bound_f64 if f64 else lib().fz_compress_bound)(ctypes.byref(dims)))
     if out is None:
         out = torch.empty(bound, dtype=torch.uint8, device=x.device)
     elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
         raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
-    rc = lib().fz_compress(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
-                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    fn = lib().fz_compress_f64 if f64 else lib().fz_compress
+    rc = fn(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
+            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     if rc:
-        raise FzError(rc, "fz_compress")
+        raise FzError(rc, "fz_compress_f64" if f64 else "fz_compress")
     return out
 
 
-def decompress(s, shape, out=None, err=None, stream=None):
-    """Decompress a stream held in a uint8 CUDA tensor into float32.  If
-    ``err`` (a 1-element int32 CUDA tensor) is given it receives 0 or the
-    error code of a stream rejected on the device."""
+def decompress(s, shape, out=None, err=None, stream=None, dtype=None):
+    """Decompress a stream held in a uint8 CUDA tensor into float32, or into
+    float64 for a stream of fp64 input (``dtype=torch.float64``, or an
+    ``out`` of that type).  If ``err`` (a 1-element int32 CUDA tensor) is
+    given it receives 0 or the error code of a stream rejected on the
+    device."""
     import torch
 
     dims = dims_of(shape)
+    if dtype is None:
+        dtype = out.dtype if out is not None else torch.float32
+    if dtype not in (torch.float32, torch.float64):
+        raise ValueError("dtype must be float32 or float64")
     if out is None:
-        out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
-    rc = lib().fz_decompress(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims),
-                             ctypes.c_void_p(err.data_ptr() if err is not None else 0), _stream_ptr(stream))
+        out = torch.empty(tuple(shape), dtype=dtype, device=s.device)
+    elif out.dtype != dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != math.prod(shape):
+        raise ValueError("out must be a contiguous %s CUDA tensor of the field's size" % dtype)
+    fn = lib().fz_decompress_f64 if dtype == torch.float64 else lib().fz_decompress
+    rc = fn(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims),
+            ctypes.c_void_p(err.data_ptr() if err is not None else 0), _stream_ptr(stream))
     if rc:
         raise FzError(rc, "fz_decompress")
     return out

@@ -26,6 +26,16 @@ void put_bytes(HeaderImage& h, int off, const void* src, int n) { std::memcpy(re
 
 namespace fz {
 
+HeaderImage header_image_f64(const Geom& g, double eb, int mode, double ebx2, double inv)
+{
+    HeaderImage h = header_image(g, eb, mode, (float)ebx2, (float)inv);
+    const uint8_t dtype = 1;
+    put_bytes(h, kOffDtype, &dtype, 1);
+    put_bytes(h, kOffEbx2F64, &ebx2, 8);
+    put_bytes(h, kOffInvF64, &inv, 8);
+    return h;
+}
+
 HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float inv)
 {
     HeaderImage h;
@@ -122,6 +132,39 @@ int fz_decompress(const void* d_stream, float* d_out, const fz_dims* dims, uint3
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
+size_t fz_compress_bound_f64(const fz_dims* dims)
+{
+    Geom g;
+    if (!geom_of(dims, &g)) return 0;
+    return (size_t)g.bound64;
+}
+
+int fz_compress_f64(const double* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
+{
+    Geom g;
+    if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != FZ_EB_ABS && eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
+    double ebx2 = 0.0, inv = 0.0;  // REL: derived on the device
+    if (eb_mode == FZ_EB_ABS) {
+        ebx2 = 2.0 * eb;
+        inv = 1.0 / ebx2;
+        if (!(ebx2 >= DBL_MIN) || !std::isfinite(ebx2) || !std::isfinite(inv) || !(inv > 0.0)) return FZ_ERR_EB_RANGE;
+    }
+    const HeaderImage h = header_image_f64(g, eb, eb_mode, ebx2, inv);
+    hipError_t e = launch_compress_f64(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
+int fz_decompress_f64(const void* d_stream, double* d_out, const fz_dims* dims, uint32_t* d_err, void* stream)
+{
+    Geom g;
+    if (!d_stream || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    hipError_t e = launch_decompress_f64(static_cast<const uint8_t*>(d_stream), d_out, g, d_err,
+                                         static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
 int fz_stream_info(const void* h_header, size_t n, fz_info* out)
 {
     if (!h_header || !out || n < (size_t)kHeaderBytes) return FZ_ERR_ARG;
@@ -150,6 +193,9 @@ int fz_stream_info(const void* h_header, size_t n, fz_info* out)
     std::memcpy(&out->total_bytes, s + kOffTotal, 8);
     Geom g;
     if (make_geom((int)out->rank, out->n, &g)) out->header_bytes = (uint64_t)g.payload_off;
+    out->dtype = s[kOffDtype];
+    std::memcpy(&out->ebx2_f64, s + kOffEbx2F64, 8);
+    std::memcpy(&out->inv_f64, s + kOffInvF64, 8);
     return FZ_OK;
 }
 

@@ -17,7 +17,7 @@
 
 namespace fz {
 
-template <int RANK, bool VEC4, bool PW>
+template <int RANK, bool VEC4, int QM>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
 {
     __shared__ CompressLds S;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         uint32_t tk;  // thread 0 only: a value on the other lanes would need a copy that waits for the atomic
         if (threadIdx.x == 0) tk = atomicAdd(&scr->ticket, 1u);
         uint64_t F[16], myflag;
-        const int nout = chunk_layer<RANK, VEC4, PW>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        const int nout = chunk_layer<RANK, VEC4, QM>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
         if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -87,19 +87,19 @@ int64_t minmax_blocks(int64_t n)
     return blocks < 1 ? 1 : blocks;
 }
 
-template <int RANK, bool VEC4, bool PW>
+template <int RANK, bool VEC4, int QM>
 static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
     // persistent grid: as many workgroups as stay resident, at most one per chunk
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4, PW>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4, QM>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     const int64_t resident = (int64_t)cus * per_cu;
     const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
-    hipLaunchKernelGGL((k_compress<RANK, VEC4, PW>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
+    hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, out, g);
@@ -108,13 +108,38 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
-                           hipStream_t st)
+static hipError_t launch_init(uint8_t* out, const Geom& g, const HeaderImage& h, hipStream_t st)
 {
     const int64_t init_threads = g.n_chunks > kHeaderBytes / 4 ? g.n_chunks : kHeaderBytes / 4;
     const unsigned init_blocks = (unsigned)((init_threads + 255) / 256 < 1024 ? (init_threads + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, out, g, h);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
+                               double eb, hipStream_t st)
+{
+    hipError_t e = launch_init(out, g, h, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_f64_front(x, out, g, mode, eb, st)) != hipSuccess) return e;
+    // the integer buffer is 256-byte aligned: whole-vector loads whenever the rows allow them
+    const int32_t* q = reinterpret_cast<const int32_t*>(out + g.q_off);
+    const float* qf = reinterpret_cast<const float*>(q);
+    const bool vec4 = g.rank == 1 || (g.n[g.rank - 1] & 3) == 0;
+    switch (g.rank * 2 + (vec4 ? 1 : 0)) {
+        case 7: return launch_rank<3, true, kQuantInt>(qf, out, g, st);
+        case 6: return launch_rank<3, false, kQuantInt>(qf, out, g, st);
+        case 5: return launch_rank<2, true, kQuantInt>(qf, out, g, st);
+        case 4: return launch_rank<2, false, kQuantInt>(qf, out, g, st);
+        case 3: return launch_rank<1, true, kQuantInt>(qf, out, g, st);
+        default: return launch_rank<1, false, kQuantInt>(qf, out, g, st);
+    }
+}
+
+hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
+                           hipStream_t st)
+{
+    hipError_t e = launch_init(out, g, h, st);
     if (e != hipSuccess) return e;
     if (mode == FZ_EB_REL) {
         const int64_t n = g.n[0] * g.n[1] * g.n[2];
@@ -127,21 +152,21 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     if (mode == FZ_EB_PWREL) {
         switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-            case 7: return launch_rank<3, true, true>(x, out, g, st);
-            case 6: return launch_rank<3, false, true>(x, out, g, st);
-            case 5: return launch_rank<2, true, true>(x, out, g, st);
-            case 4: return launch_rank<2, false, true>(x, out, g, st);
-            case 3: return launch_rank<1, true, true>(x, out, g, st);
-            default: return launch_rank<1, false, true>(x, out, g, st);
+            case 7: return launch_rank<3, true, kQuantPw>(x, out, g, st);
+            case 6: return launch_rank<3, false, kQuantPw>(x, out, g, st);
+            case 5: return launch_rank<2, true, kQuantPw>(x, out, g, st);
+            case 4: return launch_rank<2, false, kQuantPw>(x, out, g, st);
+            case 3: return launch_rank<1, true, kQuantPw>(x, out, g, st);
+            default: return launch_rank<1, false, kQuantPw>(x, out, g, st);
         }
     }
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true, false>(x, out, g, st);
-        case 6: return launch_rank<3, false, false>(x, out, g, st);
-        case 5: return launch_rank<2, true, false>(x, out, g, st);
-        case 4: return launch_rank<2, false, false>(x, out, g, st);
-        case 3: return launch_rank<1, true, false>(x, out, g, st);
-        default: return launch_rank<1, false, false>(x, out, g, st);
+        case 7: return launch_rank<3, true, kQuantGrid>(x, out, g, st);
+        case 6: return launch_rank<3, false, kQuantGrid>(x, out, g, st);
+        case 5: return launch_rank<2, true, kQuantGrid>(x, out, g, st);
+        case 4: return launch_rank<2, false, kQuantGrid>(x, out, g, st);
+        case 3: return launch_rank<1, true, kQuantGrid>(x, out, g, st);
+        default: return launch_rank<1, false, kQuantGrid>(x, out, g, st);
     }
 }
 

@@ -73,15 +73,20 @@ __device__ __forceinline__ bool finish_step(const int (&d)[32], uint32_t (&P)[16
 // prequantize 32 values; `facc` tracks max |p| with NaN propagating
 // (v_maximum3_f32), so one compare per step (!(facc < 2^31)) finds NaN, Inf
 // or an overflowing product
-template <bool PW>
+template <int QM>
 __device__ __forceinline__ void prequant32(const float (&v)[32], const Quant& z, float& facc, int (&q)[32])
 {
+    if constexpr (QM == kQuantInt) {  // the values are already the integers q (fp64 input)
+#pragma unroll
+        for (int i = 0; i < 32; i++) q[i] = __float_as_int(v[i]);
+        return;
+    }
     const float inv = z.inv;  // 0 in the point-wise mode: x * inv flags NaN/Inf there
 #pragma unroll
     for (int i = 0; i < 32; i += 2) {
         const float p0 = v[i] * inv, p1 = v[i + 1] * inv;
         facc = __builtin_elementwise_maximum(facc, __builtin_elementwise_maximum(__builtin_fabsf(p0), __builtin_fabsf(p1)));
-        if constexpr (PW) {
+        if constexpr (QM == kQuantPw) {
             q[i] = pw_quant(v[i], z);
             q[i + 1] = pw_quant(v[i + 1], z);
         } else {
@@ -280,7 +285,7 @@ __device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const
 // nz[b] collects their OR for the flags.
 // Returns whether some delta of the layer needs an escape (only the ESC pass
 // logs them).
-template <int RANK, bool EDGE, bool VEC4, bool ESC, bool PW = false>
+template <int RANK, bool EDGE, bool VEC4, bool ESC, int QM = kQuantGrid>
 __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, Quant inv,
                                       int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
                                       float& facc, EscapeLog& log)
@@ -299,13 +304,13 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
         if (RANK == 1 && k > 0) {
             uint32_t dummy = 0;
             const float xh = x[l.org[0] + (int64_t)kStepCodes * 4 * k - 1];
-            carry1 = PW ? pw_quant(xh, inv) : prequant(xh, inv.inv, dummy);
+            carry1 = QM == kQuantPw ? pw_quant(xh, inv) : QM == kQuantInt ? __float_as_int(xh) : prequant(xh, inv.inv, dummy);
         }
     } else if (RANK == 3) {
-        prequant32<PW>(h, inv, facc, qprev);
+        prequant32<QM>(h, inv, facc, qprev);
     } else {
         int qh[32];
-        prequant32<PW>(h, inv, facc, qh);
+        prequant32<QM>(h, inv, facc, qh);
 #pragma unroll
         for (int c = 0; c < 16; c++) qprev[c] = qh[16 + c];
     }
@@ -333,7 +338,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
         // arithmetic up to its loads, which would wait on them right away
         __builtin_amdgcn_sched_barrier(0);
         int q[32];
-        prequant32<PW>(v, inv, facc, q);
+        prequant32<QM>(v, inv, facc, q);
         int d[32];
         if (RANK == 3) {
             int a[32];
@@ -389,7 +394,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
 // step of the layer and `v` the one below it.  The deltas and words are those
 // of the forward sweep; escapes are only detected (the out-of-line pass logs
 // them in code order).
-template <int RANK, bool VEC4, bool PW = false>
+template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geom& g, const Lane& l, int k, Quant inv,
                                           int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
                                           float& facc, EscapeLog& log)
@@ -399,7 +404,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
 #pragma unroll
     for (int b = 0; b < 16; b++) nz[b] = 0u;
     int cq[32];  // q of the step being coded (3-D: its plane; 2-D: its two rows)
-    prequant32<PW>(h, inv, facc, cq);
+    prequant32<QM>(h, inv, facc, cq);
 #pragma unroll
     for (int it = 0; it < 4; it++) {
         const int t = 3 - it, s = 4 * k + t;
@@ -407,7 +412,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
         if (it < 3) load_step<RANK, false, VEC4>(x, g, l, s - 2, lane, vn);  // s - 2 = 4k - 1 at it = 2: the halo
         __builtin_amdgcn_sched_barrier(0);
         int ql[32];  // q of step s - 1
-        prequant32<PW>(v, inv, facc, ql);
+        prequant32<QM>(v, inv, facc, ql);
         int d[32];
         if (RANK == 3) {
             int a[32];
@@ -484,7 +489,7 @@ __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom
 // in the scratch so that nothing large crosses the call.  It stays a real
 // call: inlined, its registers would push the fast path into spills, while
 // as a call the register saves happen only on this path.
-template <int RANK, bool VEC4, bool PW = false>
+template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
                                             int64_t c, int k, Quant inv, int lane, uint32_t* Wl, uint32_t* oidx,
                                             int32_t* oval)
@@ -496,8 +501,8 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
     uint32_t nz[16];
     float facc = 0.0f;
     EscapeLog log{oidx, oval, 0};
-    if (l.edge) layer<RANK, true, VEC4, true, PW>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    else layer<RANK, false, VEC4, true, PW>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    if (l.edge) layer<RANK, true, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    else layer<RANK, false, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     return ((uint64_t)(uint32_t)log.count << 32) | __float_as_uint(facc);
 }
 
@@ -581,7 +586,7 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 // unless the chunk is cut by the field's edge (the out-of-line pass then
 // loads its own).  F receives the layer's per-plane ballots and `myflag` the
 // flag word lane b < 16 stores; returns the layer's logged escape count.
-template <int RANK, bool VEC4, bool PW = false>
+template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
                                            int64_t c, const Lane& l, int wave, int lane, Quant inv, float (&h)[32],
                                            float (&v)[32], CompressLds& S, uint64_t (&F)[16], uint64_t& myflag)
@@ -595,14 +600,14 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
         if (!slow) {
             if constexpr (RANK >= 2) {
                 slow = swept_down<RANK>(wave)
-                           ? layer_rev<RANK, VEC4, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
-                           : layer<RANK, false, VEC4, false, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+                           ? layer_rev<RANK, VEC4, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
+                           : layer<RANK, false, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
             } else {
-                slow = layer<RANK, false, VEC4, false, PW>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+                slow = layer<RANK, false, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
             }
         }
         if (slow) {  // edge chunk, or escapes to log
-            const uint64_t r = layer_slow<RANK, VEC4, PW>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
+            const uint64_t r = layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
             log.count = (int)(r >> 32);
             facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
 #pragma unroll

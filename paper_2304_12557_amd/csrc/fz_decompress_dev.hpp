@@ -18,14 +18,19 @@
 
 namespace fz {
 
-__device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank)
+// dtype: 0 for an fp32 output, 1 for fp64
+__device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank, int dtype)
 {
     const uint32_t w0 = *reinterpret_cast<const uint32_t*>(s + kOffMagic);
     const uint32_t w1 = *reinterpret_cast<const uint32_t*>(s + kOffVersion);
     if (w0 != kMagic) return 6;                                     // FZ_ERR_STREAM
     if (w1 != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16))) return 7;  // FZ_ERR_VERSION
     if (*reinterpret_cast<const uint32_t*>(s + kOffStatus) != 0u) return 8;    // FZ_ERR_STATUS
-    if (s[kOffDtype] != 0 || s[kOffRank] != rank || s[kOffEbMode] > 2) return 6;
+    if (s[kOffDtype] != dtype || s[kOffRank] != rank || s[kOffEbMode] > (dtype ? 1 : 2)) return 6;
+    if (dtype) {  // 2 eb as a normal, finite double
+        const double e2 = *reinterpret_cast<const double*>(s + kOffEbx2F64);
+        if (!(e2 >= 2.2250738585072014e-308 && e2 <= 1.7976931348623157e308)) return 6;
+    }
     if (s[kOffEbMode] == 2) {  // the point-wise mode's step: an integer in [2, 2^24)
         const float st = *reinterpret_cast<const float*>(s + kOffEbx2);
         if (!(st >= 2.0f && st < 16777216.0f) || st != __builtin_floorf(st)) return 6;
@@ -82,33 +87,38 @@ __device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], uint3
     return bad;
 }
 
-// Dequantization (Sec. 2.3): q * 2eb in fp32, or in the point-wise relative
-// mode the inverse of the bit-pattern transform with the stream's step.
-template <bool PW>
-__device__ __forceinline__ float dequant(int q, float ebx2, uint32_t step)
+// Dequantization (Sec. 2.3): q * 2eb in the output's precision (one fp32 or
+// one fp64 multiply), or in the point-wise relative mode (fp32 only) the
+// inverse of the bit-pattern transform with the stream's step.
+template <bool PW, typename T>
+__device__ __forceinline__ T dequant(int q, T ebx2, uint32_t step)
 {
     if constexpr (PW) return pw_dequant(q, step);
-    else return (float)q * ebx2;
+    else return (T)q * ebx2;
 }
 
-template <int CNT, bool VEC4, bool PW>
-__device__ __forceinline__ void store_run(float* __restrict__ p, const int* q, float ebx2, uint32_t step)
+template <int CNT, bool VEC4, bool PW, typename T>
+__device__ __forceinline__ void store_run(T* __restrict__ p, const int* q, T ebx2, uint32_t step)
 {
-    if (VEC4) {
+    if constexpr (VEC4 && sizeof(T) == 4) {
 #pragma unroll
         for (int j = 0; j < CNT / 4; j++)
             *reinterpret_cast<float4*>(p + 4 * j) =
                 make_float4(dequant<PW>(q[4 * j], ebx2, step), dequant<PW>(q[4 * j + 1], ebx2, step),
                             dequant<PW>(q[4 * j + 2], ebx2, step), dequant<PW>(q[4 * j + 3], ebx2, step));
+    } else if constexpr (VEC4) {
+#pragma unroll
+        for (int j = 0; j < CNT / 2; j++)
+            *reinterpret_cast<double2*>(p + 2 * j) =
+                make_double2(dequant<PW>(q[2 * j], ebx2, step), dequant<PW>(q[2 * j + 1], ebx2, step));
     } else {
 #pragma unroll
         for (int j = 0; j < CNT; j++) p[j] = dequant<PW>(q[j], ebx2, step);
     }
 }
 
-template <int CNT, bool PW>
-__device__ __forceinline__ void store_run_masked(float* __restrict__ p, const int* q, float ebx2, uint32_t step,
-                                                 int valid)
+template <int CNT, bool PW, typename T>
+__device__ __forceinline__ void store_run_masked(T* __restrict__ p, const int* q, T ebx2, uint32_t step, int valid)
 {
 #pragma unroll
     for (int j = 0; j < CNT; j++)
@@ -146,16 +156,18 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, float* base, 
     __syncthreads();  // the tile is rewritten by the next step
 }
 
-template <int RANK, bool VEC4, bool PW>
-__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, float* __restrict__ y, const Geom& g,
+template <int RANK, bool VEC4, bool PW, typename T>
+__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, T* __restrict__ y, const Geom& g,
                                                  uint32_t* d_err, int64_t c, int lane, float* tile)
 {
-    const uint32_t hdr_err = check_header(s, g, RANK);
+    constexpr bool F64 = sizeof(T) == 8;
+    const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0);
     if (hdr_err) {
         if (c == 0 && lane == 0 && d_err) atomicCAS(d_err, 0u, hdr_err);
         return;
     }
-    const float ebx2 = *reinterpret_cast<const float*>(s + kOffEbx2);
+    const T ebx2 = F64 ? (T)*reinterpret_cast<const double*>(s + kOffEbx2F64)
+                       : (T)*reinterpret_cast<const float*>(s + kOffEbx2);
     const uint32_t step = PW ? (uint32_t)ebx2 : 0u;  // the point-wise mode's step (checked by check_header)
     const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
     const uint64_t payload_units = (total - g.payload_off) / 16;
@@ -290,7 +302,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 #pragma unroll
                     for (int r = 0; r < 4; r++)
                         if (r < ey) store_run_masked<8, PW>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, step, ex);
-                } else if (VEC4) {
+                } else if constexpr (VEC4 && !F64) {
                     // the plane goes through LDS so that every store instruction
                     // writes 4 whole rows of 64 values (a lane's own 4x8 patch
                     // would give each instruction half-filled 32-byte pieces)
@@ -330,8 +342,8 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     for (int cc = 1; cc < 16; cc++) d[16 * r + cc] += d[16 * r + cc - 1];
 #pragma unroll
                 for (int r = 0; r < 2; r++) {
-                    const int T = d[16 * r + 15];
-                    const int ex_ = wave_incl_scan(T, lane) - T;
+                    const int tot = d[16 * r + 15];
+                    const int ex_ = wave_incl_scan(tot, lane) - tot;
 #pragma unroll
                     for (int cc = 0; cc < 16; cc++) d[16 * r + cc] += ex_;
                 }
@@ -346,7 +358,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     const int ex = clampi(ext[1] - 16 * lane, 0, 16);
                     store_run_masked<16, PW>(y + (yy * g.n[1] + x0), d, ebx2, step, ex);
                     if (2 * st + 1 < ext[0]) store_run_masked<16, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step, ex);
-                } else if (VEC4) {
+                } else if constexpr (VEC4 && !F64) {
                     // through LDS, so that every store writes 1 KiB of one row
 #pragma unroll
                     for (int r = 0; r < 2; r++)
@@ -366,8 +378,8 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             } else {
 #pragma unroll
                 for (int m = 1; m < 32; m++) d[m] += d[m - 1];
-                const int T = d[31];
-                const int ex_ = wave_incl_scan(T, lane) - T + carry1;
+                const int tot = d[31];
+                const int ex_ = wave_incl_scan(tot, lane) - tot + carry1;
 #pragma unroll
                 for (int m = 0; m < 32; m++) d[m] += ex_;
                 carry1 = __builtin_amdgcn_readlane(d[31], 63);
@@ -375,7 +387,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                 if (edge) {
                     const int valid = clampi(ext[0] - ((int64_t)kStepCodes * st + kPatchCodes * lane), 0, 32);
                     store_run_masked<32, PW>(y + x0, d, ebx2, step, valid);
-                } else if (VEC4) {
+                } else if constexpr (VEC4 && !F64) {
 #pragma unroll
                     for (int j = 0; j < 8; j++) {
                         const int* q = d + 4 * j;
@@ -398,12 +410,16 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 
 // Decompress chunk c with the stream's quantizer (the mode byte is uniform:
 // one of the two bodies runs).
-template <int RANK, bool VEC4>
-__device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, float* __restrict__ y,
+template <int RANK, bool VEC4, typename T>
+__device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, T* __restrict__ y,
                                                      const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
 {
-    if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true>(s, y, g, d_err, c, lane, tile);
-    else decompress_chunk<RANK, VEC4, false>(s, y, g, d_err, c, lane, tile);
+    if constexpr (sizeof(T) == 8) {
+        decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);  // fp64: grid modes only
+    } else {
+        if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true, T>(s, y, g, d_err, c, lane, tile);
+        else decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);
+    }
 }
 
 }  // namespace fz

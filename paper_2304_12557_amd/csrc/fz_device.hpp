@@ -106,6 +106,12 @@ __device__ __forceinline__ int prequant(float v, float inv, uint32_t& acc)
 
 __device__ __forceinline__ uint32_t absu(int d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
 
+// how k_compress turns its input words into the integers q: fp32 values on
+// the grid 2eb (Sec. 2.3), fp32 values through the point-wise relative
+// transform, or words that already hold q (fp64 input, prequantized by a
+// pass of its own)
+constexpr int kQuantGrid = 0, kQuantPw = 1, kQuantInt = 2;
+
 // The quantizer a stream records.  step == 0: the 2eb grid of the ABS and REL
 // modes, q = rint(x * inv).  step > 0: the point-wise relative mode, where
 // the data's logarithmic transform is the float's bit pattern b (exponent and

@@ -46,6 +46,8 @@ constexpr int64_t kChunkPayloadBound = (int64_t)kLayers * kPlanes * kPatches * 1
 constexpr int kOffMagic = 0, kOffVersion = 4, kOffHdrBytes = 6, kOffStatus = 8, kOffDtype = 12, kOffRank = 13,
               kOffEbMode = 14, kOffDims = 16, kOffEbUser = 40, kOffEbx2 = 48, kOffInv = 52, kOffVmin = 56,
               kOffVmax = 60, kOffChunk = 64, kOffNChunks = 72, kOffNnz = 80, kOffNout = 88, kOffTotal = 96;
+// fp64 streams (dtype 1): 2 eb_abs and its reciprocal as doubles (zero in fp32 streams)
+constexpr int kOffEbx2F64 = 104, kOffInvF64 = 112;
 
 // status bits
 constexpr uint32_t kErrNonfinite = 1u, kErrEbRange = 2u, kErrOutlierCap = 4u;
@@ -80,7 +82,13 @@ struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into
     int64_t table_off, flags_off, payload_off;  // = header bytes
     int64_t scratch_off, minmax_off, stage_off;  // scratch after the worst-case stream
     int64_t bound;                               // bound includes the scratch and the staging
+    // fp64 input: the prequantized integers (4 B per value) and the partial
+    // value ranges of its REL pass follow the fp32 bound
+    int64_t q_off, part64_off, bound64;
 };
+// per-block partials of the fp64 range pass: min and max (2 doubles), then a
+// u32 non-finite flag per block after all the doubles
+constexpr int64_t kPart64Bytes = 20 * kMinmaxBlocks;
 
 inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
 {
@@ -112,6 +120,10 @@ inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
     g->minmax_off = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
     g->stage_off = (g->minmax_off + 16 * kMinmaxBlocks + 255) / 256 * 256;
     g->bound = g->stage_off + g->n_chunks * kStageSlotBytes;
+    const int64_t n = g->n[0] * g->n[1] * g->n[2];  // below 2^46: fewer than 2^31 chunks of 2^15 values
+    g->q_off = (g->bound + 255) / 256 * 256;
+    g->part64_off = g->q_off + (4 * n + 255) / 256 * 256;
+    g->bound64 = g->part64_off + kPart64Bytes;
     return true;
 }
 

@@ -14,11 +14,20 @@ struct HeaderImage {
 hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
                            hipStream_t st);
 hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);
+// fp64 input (FZ_EB_ABS or FZ_EB_REL): the range pass (REL) and the
+// prequantization into the integer buffer at g.q_off, then the compression
+// kernel on those integers
+hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
+                               double eb, hipStream_t st);
+hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mode, double eb, hipStream_t st);
+hipError_t launch_decompress_f64(const uint8_t* s, double* y, const Geom& g, uint32_t* d_err, hipStream_t st);
 
 // blocks of the REL range pass of a field of n values
 int64_t minmax_blocks(int64_t n);
 // header image of a stream (magic, version, dims, eb, chunk box, ...)
 HeaderImage header_image(const Geom& g, double eb, int mode, float ebx2, float inv);
+// the same for an fp64 stream (dtype 1; the double parameters at their own offsets)
+HeaderImage header_image_f64(const Geom& g, double eb, int mode, double ebx2, double inv);
 // eb parameters of an absolute bound; false if unusable
 bool abs_params(double eb, float* ebx2, float* inv);
 // the header's quantizer fields for a bound and mode, as far as the host

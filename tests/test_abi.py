@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "fz.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fz_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fz_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -50,6 +50,12 @@ def test_argument_errors_return_immediately():
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-8, 2, ctypes.c_void_p(16), None) == 4
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1.1e-7, 2, ctypes.c_void_p(16), None) == 4
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 3, ctypes.c_void_p(16), None) == 1
+    # fp64 input: grid modes only; 2 eb below the smallest normal double is out of range
+    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 2, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress_f64(None, ctypes.byref(d), 1e-3, 0, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), float("inf"), 0, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), 1e-310, 0, ctypes.c_void_p(16), None) == 4
+    assert L.fz_decompress_f64(None, ctypes.c_void_p(16), ctypes.byref(d), None, None) == 1
     bad = fz.FzDims()
     bad.rank = 4
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(bad), 1e-3, 1, ctypes.c_void_p(16), None) == 1
@@ -169,3 +175,12 @@ def test_ablation_argument_errors():
     assert L.fz_abl_pred_quant(2, p, ctypes.byref(good), 0.0, p, None, None) == 1
     assert L.fz_abl_pred_quant(2, None, ctypes.byref(good), 100.0, p, None, None) == 1
     assert L.fz_abl_encode(p, p, ctypes.byref(good), None, p, None) == 1
+
+
+@pytest.mark.parametrize("shape", [(1,), (70001,), (45, 1030), (20, 40, 70), (512, 512, 512)])
+def test_f64_bound(shape):
+    """The fp64 output buffer holds the fp32 one plus the integers q and the
+    range pass's partials."""
+    n = int(np.prod(shape))
+    b32, b64 = fz.compress_bound(shape), fz.compress_bound(shape, f64=True)
+    assert b64 >= b32 + 4 * n and b64 % 4 == 0
