@@ -437,6 +437,45 @@ def pointwise_relative(xt, shape, stream, reps):
     return rows
 
 
+def fp64_input(xt, shape, eb, stream, reps):
+    """fp64 input: the same field widened to double, REL bound eb.  Compress
+    and decompress time (HIP events) over the 8-byte input values, ratio,
+    and the largest error over the absolute bound."""
+    import numpy as np
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    x64 = xt.double()
+    buf = torch.empty(fz.compress_bound(shape, f64=True), dtype=torch.uint8, device=xt.device)
+    y = torch.empty_like(x64)
+    fz.compress(x64, eb, "rel", out=buf)
+    fz.decompress(buf, shape, out=y)
+    torch.cuda.synchronize()
+    info = fz.stream_info(buf)
+    if info["status"]:
+        return {"eb": eb, "status": int(info["status"])}
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for k in range(reps):
+        ev[k][0].record(stream)
+        fz.compress(x64, eb, "rel", out=buf)
+        ev[k][1].record(stream)
+        fz.decompress(buf, shape, out=y)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    tc = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    td = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    in_bytes = 8 * xt.numel()
+    err = (y - x64).abs().max().item()
+    out = {"eb": eb, "ratio": round(in_bytes / int(info["total_bytes"]), 3),
+           "compress_GBps": round(in_bytes / 1e9 / (tc * 1e-3), 2),
+           "decompress_GBps": round(in_bytes / 1e9 / (td * 1e-3), 2),
+           "max_err_over_eb": round(err / (0.5 * info["ebx2_f64"]), 6)}
+    del x64, y, buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def overall_throughput(xt, shape, eb, s_bytes, t_compr_gbps, steps):
     """Overall data-transfer throughput (Sec. 4.6): compress on the device,
     then move the stream to pinned host memory.  Reports the measured
@@ -626,6 +665,7 @@ def main():
         out["overall_throughput"] = overall_throughput(xt, shape, a.eb, s_bytes, in_bytes / 1e9 / (tc * 1e-3),
                                                        a.steps)
         out["pointwise_relative"] = pointwise_relative(xt, shape, stream, a.steps)
+        out["fp64_input"] = fp64_input(xt, shape, a.eb, stream, a.steps)
     if not a.no_ablation:
         out["ablation"] = bench_ablation(xt, float(info["inv"]), tca)
     if not a.no_layers:
