@@ -73,6 +73,7 @@ typedef struct {
     int64_t box[3];  /* chunk box, same order */
     int64_t grid[3]; /* chunks per dimension */
     int64_t n_chunks;
+    int global; /* Lorenzo predictor over the whole field (1) or inside each chunk (0) */
 } geom_t;
 
 static int make_geom(int rank, const int64_t *dims, geom_t *g)
@@ -266,8 +267,13 @@ float fzo_dequant_pw(int32_t q, uint32_t step)
  * a zero ghost.  Wrapping 32-bit arithmetic.                              */
 static uint32_t qat(const geom_t *g, const int32_t *q, const int64_t o[3], int64_t a, int64_t b, int64_t c)
 {
-    /* a, b, c are box-relative; negative means ghost */
-    if (a < 0 || b < 0 || c < 0) return 0u;
+    /* a, b, c are box-relative; a ghost is a neighbour before the chunk's
+     * origin (chunk-local predictor) or before the field's (O3g) */
+    if (g->global) {
+        if (o[0] + a < 0 || o[1] + b < 0 || o[2] + c < 0) return 0u;
+    } else if (a < 0 || b < 0 || c < 0) {
+        return 0u;
+    }
     return (uint32_t)q[lin(g, o[0] + a, o[1] + b, o[2] + c)];
 }
 
@@ -398,7 +404,7 @@ static void encode_chunk(const geom_t *g, const int32_t *q, int64_t c, chunk_out
  * offsets with a prefix sum).                                             */
 /* the header fields that depend on the input type and the bound */
 typedef struct {
-    int dtype, eb_mode;
+    int dtype, eb_mode, predictor;
     double eb;
     float ebx2, inv, vmin, vmax;
     double ebx2_64, inv_64; /* fp64 input only (bytes 104 and 112; 0 otherwise) */
@@ -410,8 +416,21 @@ static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const 
 int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, int eb_mode,
                      uint8_t *out, int64_t cap, uint32_t *status_out, int threads)
 {
+    return fzo_compress_pred(x, rank, dims, eb, eb_mode, 0, out, cap, status_out, threads);
+}
+
+/* O3g: the field-global Lorenzo predictor (the classic form, Sec. 2.3): the
+ * same difference operator over the whole field, a neighbour outside the
+ * field being a zero ghost, so that chunk borders are predicted from the
+ * neighbouring chunk's values.  The deltas are then coded per chunk exactly
+ * as in the chunk-local stream; header byte 15 records the predictor.     */
+int64_t fzo_compress_pred(const float *x, int rank, const int64_t *dims, double eb, int eb_mode, int global,
+                          uint8_t *out, int64_t cap, uint32_t *status_out, int threads)
+{
     geom_t g;
     if (make_geom(rank, dims, &g)) return -1;
+    if (global != 0 && global != 1) return -1;
+    g.global = global;
     if (!(eb > 0.0) || !isfinite(eb) || (eb_mode != FZO_EB_ABS && eb_mode != FZO_EB_REL && eb_mode != FZO_EB_PWREL))
         return -1;
     int64_t N = g.n[0] * g.n[1] * g.n[2];
@@ -422,6 +441,7 @@ int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, i
     h.dtype = 0;
     h.eb_mode = eb_mode;
     h.eb = eb;
+    h.predictor = global;
     uint32_t status = (uint32_t)fzo_eb_params(x, N, eb, eb_mode, &h.ebx2, &h.inv, &h.vmin, &h.vmax);
     int32_t *q = (int32_t *)calloc((size_t)N, sizeof(int32_t));
     if (!status)
@@ -576,6 +596,7 @@ static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const 
     out[12] = (uint8_t)h->dtype; /* 0 f32, 1 f64 */
     out[13] = (uint8_t)rank;
     out[14] = (uint8_t)h->eb_mode;
+    out[15] = (uint8_t)h->predictor; /* 0 chunk-local Lorenzo, 1 field-global */
     for (int i = 0; i < 3; i++) put64(out + 16 + 8 * i, (uint64_t)g.n[i]);
     memcpy(out + 40, &h->eb, 8);
     memcpy(out + 48, &h->ebx2, 4);
@@ -622,7 +643,8 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
     if (get32(s) != FZO_MAGIC) return FZO_DERR_STREAM;
     if (get16(s + 4) != FZO_VERSION || get16(s + 6) != FZO_HEADER_BYTES) return FZO_DERR_VERSION;
     if (get32(s + 8) != 0) return FZO_DERR_STATUS;
-    if (s[12] != (x64 ? 1 : 0) || s[13] != rank) return FZO_DERR_STREAM;
+    if (s[12] != (x64 ? 1 : 0) || s[13] != rank || s[15] > 1) return FZO_DERR_STREAM;
+    g.global = s[15];
     for (int i = 0; i < 3; i++)
         if ((int64_t)get64(s + 16 + 8 * i) != g.n[i]) return FZO_DERR_STREAM;
     if ((int64_t)get32(s + 72) != g.n_chunks) return FZO_DERR_STREAM;
@@ -652,6 +674,10 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
     uint16_t *codes = (uint16_t *)malloc(FZO_CHUNK_CODES * sizeof(uint16_t));
     int32_t *delta = (int32_t *)malloc(FZO_CHUNK_CODES * sizeof(int32_t));
     uint32_t *box = (uint32_t *)malloc(FZO_CHUNK_CODES * sizeof(uint32_t));
+    /* field-global predictor: every chunk's deltas go to one field, summed
+     * over the whole field once all chunks are read */
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    uint32_t *field = g.global ? (uint32_t *)calloc((size_t)N, sizeof(uint32_t)) : NULL;
     int err = 0;
     int64_t units_seen = 0;
     for (int64_t c = 0; c < g.n_chunks && !err; c++) {
@@ -706,6 +732,13 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
                          (int)(n % FZO_PATCH_CODES), r);
             if (r[0] < e0 && r[1] < e1 && r[2] < e2) box[(r[0] * e1 + r[1]) * e2 + r[2]] = (uint32_t)delta[n];
         }
+        if (g.global) {
+            for (int64_t a = 0; a < e0; a++)
+                for (int64_t b = 0; b < e1; b++)
+                    for (int64_t cc = 0; cc < e2; cc++)
+                        field[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = box[(a * e1 + b) * e2 + cc];
+            continue;
+        }
         /* D5: inclusive prefix sums along the fastest dim, then the middle,
          * then the slowest (only the dims the rank has) */
         for (int64_t a = 0; a < e0; a++)
@@ -726,6 +759,26 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
                         mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)box[(a * e1 + b) * e2 + cc], step)
                                              : (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
     }
+    if (!err && g.global) {
+        /* D5g: inclusive prefix sums of the deltas along the fastest dim,
+         * then the middle, then the slowest, over the whole field (mod 2^32);
+         * D6 as above */
+        const int64_t n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+        for (int64_t a = 0; a < n0; a++)
+            for (int64_t b = 0; b < n1; b++)
+                for (int64_t cc = 1; cc < n2; cc++) field[(a * n1 + b) * n2 + cc] += field[(a * n1 + b) * n2 + cc - 1];
+        for (int64_t a = 0; a < n0; a++)
+            for (int64_t b = 1; b < n1; b++)
+                for (int64_t cc = 0; cc < n2; cc++) field[(a * n1 + b) * n2 + cc] += field[(a * n1 + b - 1) * n2 + cc];
+        for (int64_t a = 1; a < n0; a++)
+            for (int64_t b = 0; b < n1; b++)
+                for (int64_t cc = 0; cc < n2; cc++) field[(a * n1 + b) * n2 + cc] += field[((a - 1) * n1 + b) * n2 + cc];
+        for (int64_t i = 0; i < N; i++) {
+            if (x64) x64[i] = (double)(int32_t)field[i] * ebx2_64;
+            else x[i] = mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)field[i], step) : (float)(int32_t)field[i] * ebx2;
+        }
+    }
+    free(field);
     free(codes); free(delta); free(box);
     if (!err && H + 16 * units_seen != total) err = FZO_DERR_STREAM;
     return err;

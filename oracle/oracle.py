@@ -62,6 +62,9 @@ def lib():
         L.fzo_compress.restype = ctypes.c_int64
         L.fzo_decompress.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int, _i64p]
         L.fzo_decompress.restype = ctypes.c_int
+        L.fzo_compress_pred.argtypes = [vp, ctypes.c_int, _i64p, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
+                                        ctypes.c_int64, vp, ctypes.c_int]
+        L.fzo_compress_pred.restype = ctypes.c_int64
         L.fzo_eb_params_f64.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.fzo_eb_params_f64.restype = ctypes.c_int
         L.fzo_prequant_f64.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
@@ -151,14 +154,16 @@ def chunk_codes(x, inv, c):
     return out[:n]
 
 
-def compress(x, eb, mode=EB_REL, threads=1):
-    """Returns (stream bytes as np.uint8, status)."""
+def compress(x, eb, mode=EB_REL, threads=1, global_lorenzo=False):
+    """Returns (stream bytes as np.uint8, status).  global_lorenzo: predict
+    across chunk borders (the field-global Lorenzo predictor)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     r, d = _dims(x.shape)
     cap = lib().fzo_bound(r, d)
     out = np.zeros(cap, dtype=np.uint8)
     st = np.zeros(1, dtype=np.uint32)
-    n = lib().fzo_compress(_ptr(x), r, d, float(eb), int(mode), _ptr(out), cap, _ptr(st), int(threads))
+    n = lib().fzo_compress_pred(_ptr(x), r, d, float(eb), int(mode), 1 if global_lorenzo else 0, _ptr(out), cap,
+                                _ptr(st), int(threads))
     if n < 0:
         raise ValueError("oracle compress failed: %d" % n)
     return out[:n].copy(), int(st[0])
