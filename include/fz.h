@@ -83,7 +83,7 @@ typedef struct {
     uint64_t total_bytes; /* stream size */
     uint64_t header_bytes;/* header + chunk table + flags */
     uint32_t dtype;       /* input type: 0 fp32, 1 fp64 */
-    uint32_t reserved;
+    uint32_t predictor;   /* Lorenzo predictor: 0 inside each chunk, 1 over the whole field */
     double ebx2_f64;      /* fp64 streams: 2 * absolute error bound, in double (0 for fp32) */
     double inv_f64;       /* fp64 streams: 1 / ebx2_f64 (0 for fp32) */
 } fz_info;
@@ -167,6 +167,33 @@ int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint3
 size_t fz_compress_bound_f64(const fz_dims *dims);
 int fz_compress_f64(const double *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
 int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
+
+/* ------------------------------------------- field-global Lorenzo predictor
+ * The classic Lorenzo predictor over the whole field (Sec. 2.3) instead of
+ * inside each chunk: a chunk's border cells are predicted from the
+ * neighbouring chunk's values (a neighbour outside the field counts 0).  The
+ * deltas are coded per chunk exactly as in the chunk-local stream; header
+ * byte 15 is 1.  Reconstructions are the same values as with the chunk-local
+ * predictor (every stage after prequantization is lossless); only the ratio
+ * and the cost differ.  fp32 input, any eb_mode.
+ *
+ * fz_compress_bound_global: bytes of d_out for fz_compress_global (the fp32
+ * bound plus 4 B per value for the integers the chunk kernel reads).
+ * fz_compress_global: as fz_compress, with the same arguments and errors.
+ * fz_decompress_global_work_bytes: device scratch fz_decompress_global needs
+ * (one u32 carry per chunk-box segment of every line along each axis: about
+ * N/4 bytes for a 3-D field); 0 on invalid dims.
+ * fz_decompress_global: as fz_decompress, plus d_work (that many bytes,
+ * device, overwritten).  It writes d_out in several passes (the chunk kernel's
+ * local sums, then the carries along each axis), so a rejected stream
+ * (*d_err set) leaves d_out unspecified.  fz_decompress and the batch layer
+ * reject field-global streams (FZ_ERR_STREAM), and fz_decompress_global
+ * rejects chunk-local ones. */
+size_t fz_compress_bound_global(const fz_dims *dims);
+int fz_compress_global(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
+size_t fz_decompress_global_work_bytes(const fz_dims *dims);
+int fz_decompress_global(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *d_work,
+                         void *stream);
 
 /* ------------------------------------------------------------ batches
  * Many fields of uneven rank and size in a fixed, small number of launches

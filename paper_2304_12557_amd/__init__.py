@@ -39,7 +39,7 @@ class FzInfo(ctypes.Structure):
                 ("ebx2", ctypes.c_float), ("inv", ctypes.c_float), ("vmin", ctypes.c_float),
                 ("vmax", ctypes.c_float), ("n_chunks", ctypes.c_uint32), ("nnz_blocks", ctypes.c_uint64),
                 ("n_outliers", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
-                ("header_bytes", ctypes.c_uint64), ("dtype", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("header_bytes", ctypes.c_uint64), ("dtype", ctypes.c_uint32), ("predictor", ctypes.c_uint32),
                 ("ebx2_f64", ctypes.c_double), ("inv_f64", ctypes.c_double)]
 
 
@@ -102,6 +102,14 @@ def lib():
         L.fz_compress_f64.restype = ctypes.c_int
         L.fz_decompress_f64.argtypes = [vp, vp, dp, vp, vp]
         L.fz_decompress_f64.restype = ctypes.c_int
+        L.fz_compress_bound_global.argtypes = [dp]
+        L.fz_compress_bound_global.restype = ctypes.c_size_t
+        L.fz_compress_global.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
+        L.fz_compress_global.restype = ctypes.c_int
+        L.fz_decompress_global_work_bytes.argtypes = [dp]
+        L.fz_decompress_global_work_bytes.restype = ctypes.c_size_t
+        L.fz_decompress_global.argtypes = [vp, vp, dp, vp, vp, vp]
+        L.fz_decompress_global.restype = ctypes.c_int
         L.fz_stream_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(FzInfo)]
         L.fz_stream_info.restype = ctypes.c_int
         L.fz_strerror.argtypes = [ctypes.c_int]
@@ -150,7 +158,8 @@ SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
            "fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark", "fz_abl_encode",
-           "fz_compress_bound_f64", "fz_compress_f64", "fz_decompress_f64"]
+           "fz_compress_bound_f64", "fz_compress_f64", "fz_decompress_f64", "fz_compress_bound_global",
+           "fz_compress_global", "fz_decompress_global_work_bytes", "fz_decompress_global"]
 FZ_REQ_COMPRESS = 0
 FZ_REQ_DECOMPRESS = 1
 
@@ -166,10 +175,11 @@ def dims_of(shape):
     return d
 
 
-def compress_bound(shape, f64=False):
-    """Output bytes ``compress`` needs for a field of this shape (fp32, or
-    fp64 input with ``f64=True``)."""
-    fn = lib().fz_compress_bound_f64 if f64 else lib().fz_compress_bound
+def compress_bound(shape, f64=False, global_lorenzo=False):
+    """Output bytes ``compress`` needs for a field of this shape (fp32, fp64
+    input with ``f64=True``, or the field-global predictor)."""
+    fn = (lib().fz_compress_bound_f64 if f64 else
+          lib().fz_compress_bound_global if global_lorenzo else lib().fz_compress_bound)
     return int(fn(ctypes.byref(dims_of(shape))))
 
 
@@ -195,30 +205,33 @@ def _mode(mode):
     raise ValueError("mode must be 'rel', 'abs' or 'pwrel'")
 
 
-def compress(x, eb, mode="rel", out=None, stream=None):
+def compress(x, eb, mode="rel", out=None, stream=None, global_lorenzo=False):
     """Compress a float32 or float64 CUDA tensor; returns the uint8 output
-    buffer (``compress_bound(shape, x.dtype)`` bytes; the stream occupies its
-    first ``stream_size(buf)`` bytes).  Asynchronous on ``stream``."""
+    buffer (``compress_bound`` bytes; the stream occupies its first
+    ``stream_size(buf)`` bytes).  ``global_lorenzo``: the field-global
+    predictor (float32 input).  Asynchronous on ``stream``."""
     import torch
 
     if not (x.is_cuda and x.dtype in (torch.float32, torch.float64) and x.is_contiguous()):
         raise ValueError("x must be a contiguous float32 or float64 CUDA tensor")
     f64 = x.dtype == torch.float64
+    if f64 and global_lorenzo:
+        raise ValueError("the field-global predictor takes float32 input")
     dims = dims_of(x.shape)
-    bound = int((lib().fz_compress_bound_f64 if f64 else lib().fz_compress_bound)(ctypes.byref(dims)))
+    bound = compress_bound(x.shape, f64=f64, global_lorenzo=global_lorenzo)
     if out is None:
         out = torch.empty(bound, dtype=torch.uint8, device=x.device)
     elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
         raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
-    fn = lib().fz_compress_f64 if f64 else lib().fz_compress
+    fn = lib().fz_compress_f64 if f64 else lib().fz_compress_global if global_lorenzo else lib().fz_compress
     rc = fn(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     if rc:
-        raise FzError(rc, "fz_compress_f64" if f64 else "fz_compress")
+        raise FzError(rc, "fz_compress")
     return out
 
 
-def decompress(s, shape, out=None, err=None, stream=None, dtype=None):
+def decompress(s, shape, out=None, err=None, stream=None, dtype=None, global_lorenzo=False, work=None):
     """Decompress a stream held in a uint8 CUDA tensor into float32, or into
     float64 for a stream of fp64 input (``dtype=torch.float64``, or an
     ``out`` of that type).  If ``err`` (a 1-element int32 CUDA tensor) is
@@ -235,9 +248,23 @@ def decompress(s, shape, out=None, err=None, stream=None, dtype=None):
         out = torch.empty(tuple(shape), dtype=dtype, device=s.device)
     elif out.dtype != dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != math.prod(shape):
         raise ValueError("out must be a contiguous %s CUDA tensor of the field's size" % dtype)
-    fn = lib().fz_decompress_f64 if dtype == torch.float64 else lib().fz_decompress
-    rc = fn(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims),
-            ctypes.c_void_p(err.data_ptr() if err is not None else 0), _stream_ptr(stream))
+    errp = ctypes.c_void_p(err.data_ptr() if err is not None else 0)
+    if global_lorenzo:  # a stream of the field-global predictor (header byte 15 = 1)
+        if dtype != torch.float32:
+            raise ValueError("the field-global predictor takes float32 fields")
+        nwork = int(lib().fz_decompress_global_work_bytes(ctypes.byref(dims)))
+        if work is None:  # freed when this returns: keep it until the launch's stream has passed it
+            work = torch.empty(max(nwork, 16), dtype=torch.uint8, device=s.device)
+            work.record_stream(stream if stream is not None else torch.cuda.current_stream())
+        elif work.numel() < nwork or not work.is_cuda:
+            raise ValueError("work must be a CUDA tensor of at least %d bytes" % nwork)
+        rc = lib().fz_decompress_global(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.byref(dims), errp, ctypes.c_void_p(work.data_ptr()),
+                                        _stream_ptr(stream))
+    else:
+        fn = lib().fz_decompress_f64 if dtype == torch.float64 else lib().fz_decompress
+        rc = fn(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims), errp,
+                _stream_ptr(stream))
     if rc:
         raise FzError(rc, "fz_decompress")
     return out

@@ -165,6 +165,45 @@ int fz_decompress_f64(const void* d_stream, double* d_out, const fz_dims* dims, 
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
+size_t fz_compress_bound_global(const fz_dims* dims)
+{
+    Geom g;
+    if (!geom_of(dims, &g)) return 0;
+    return (size_t)g.bound64;  // the fp32 bound, then the integers the chunk kernel reads
+}
+
+int fz_compress_global(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
+{
+    Geom g;
+    if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    float ebx2 = 0.0f, inv = 0.0f;
+    const int rc = bound_params(eb, eb_mode, &ebx2, &inv);
+    if (rc != FZ_OK) return rc;
+    HeaderImage h = header_image(g, eb, eb_mode, ebx2, inv);
+    const uint8_t global = 1;
+    put_bytes(h, kOffPredictor, &global, 1);
+    hipError_t e = launch_compress_global(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
+size_t fz_decompress_global_work_bytes(const fz_dims* dims)
+{
+    Geom g;
+    if (!geom_of(dims, &g)) return 0;
+    return global_work_bytes(g);
+}
+
+int fz_decompress_global(const void* d_stream, float* d_out, const fz_dims* dims, uint32_t* d_err, void* d_work,
+                         void* stream)
+{
+    Geom g;
+    if (!d_stream || !d_out || !d_work || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    hipError_t e = launch_decompress_global(static_cast<const uint8_t*>(d_stream), d_out, g, d_err, d_work,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
 int fz_stream_info(const void* h_header, size_t n, fz_info* out)
 {
     if (!h_header || !out || n < (size_t)kHeaderBytes) return FZ_ERR_ARG;
@@ -194,6 +233,7 @@ int fz_stream_info(const void* h_header, size_t n, fz_info* out)
     Geom g;
     if (make_geom((int)out->rank, out->n, &g)) out->header_bytes = (uint64_t)g.payload_off;
     out->dtype = s[kOffDtype];
+    out->predictor = s[kOffPredictor];
     std::memcpy(&out->ebx2_f64, s + kOffEbx2F64, 8);
     std::memcpy(&out->inv_f64, s + kOffInvF64, 8);
     return FZ_OK;

@@ -116,12 +116,9 @@ static hipError_t launch_init(uint8_t* out, const Geom& g, const HeaderImage& h,
     return hipGetLastError();
 }
 
-hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
-                               double eb, hipStream_t st)
+// the compression kernel on the integer buffer at g.q_off
+static hipError_t launch_main_int(uint8_t* out, const Geom& g, hipStream_t st)
 {
-    hipError_t e = launch_init(out, g, h, st);
-    if (e != hipSuccess) return e;
-    if ((e = launch_f64_front(x, out, g, mode, eb, st)) != hipSuccess) return e;
     // the integer buffer is 256-byte aligned: whole-vector loads whenever the rows allow them
     const int32_t* q = reinterpret_cast<const int32_t*>(out + g.q_off);
     const float* qf = reinterpret_cast<const float*>(q);
@@ -134,6 +131,36 @@ hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, con
         case 3: return launch_rank<1, true, kQuantInt>(qf, out, g, st);
         default: return launch_rank<1, false, kQuantInt>(qf, out, g, st);
     }
+}
+
+hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
+                               double eb, hipStream_t st)
+{
+    hipError_t e = launch_init(out, g, h, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_f64_front(x, out, g, mode, eb, st)) != hipSuccess) return e;
+    return launch_main_int(out, g, st);
+}
+
+static hipError_t launch_range(const float* x, uint8_t* out, const Geom& g, double eb, hipStream_t st)
+{
+    const int64_t n = g.n[0] * g.n[1] * g.n[2];
+    const int64_t blocks = minmax_blocks(n);
+    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, g, eb, (int)blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
+                                  double eb, hipStream_t st)
+{
+    hipError_t e = launch_init(out, g, h, st);
+    if (e != hipSuccess) return e;
+    if (mode == FZ_EB_REL && (e = launch_range(x, out, g, eb, st)) != hipSuccess) return e;
+    if ((e = launch_face(x, out, g, st)) != hipSuccess) return e;
+    return launch_main_int(out, g, st);
 }
 
 hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,

@@ -13,13 +13,17 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fz_device.hpp"
 #include "fz_format.hpp"
 
 namespace fz {
 
-// dtype: 0 for an fp32 output, 1 for fp64
-__device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank, int dtype)
+// dtype: 0 for an fp32 output, 1 for fp64; predictor: the header byte 15
+// the caller handles (0 chunk-local Lorenzo, 1 field-global)
+__device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank, int dtype,
+                                                 int predictor)
 {
     const uint32_t w0 = *reinterpret_cast<const uint32_t*>(s + kOffMagic);
     const uint32_t w1 = *reinterpret_cast<const uint32_t*>(s + kOffVersion);
@@ -27,6 +31,7 @@ __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, 
     if (w1 != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16))) return 7;  // FZ_ERR_VERSION
     if (*reinterpret_cast<const uint32_t*>(s + kOffStatus) != 0u) return 8;    // FZ_ERR_STATUS
     if (s[kOffDtype] != dtype || s[kOffRank] != rank || s[kOffEbMode] > (dtype ? 1 : 2)) return 6;
+    if (s[kOffPredictor] != predictor) return 6;
     if (dtype) {  // 2 eb as a normal, finite double
         const double e2 = *reinterpret_cast<const double*>(s + kOffEbx2F64);
         if (!(e2 >= 2.2250738585072014e-308 && e2 <= 1.7976931348623157e308)) return 6;
@@ -93,14 +98,27 @@ __device__ __forceinline__ uint32_t apply_escapes(const uint32_t (&P)[16], uint3
 template <bool PW, typename T>
 __device__ __forceinline__ T dequant(int q, T ebx2, uint32_t step)
 {
-    if constexpr (PW) return pw_dequant(q, step);
+    if constexpr (std::is_integral_v<T>) return q;  // the integers themselves (field-global predictor)
+    else if constexpr (PW) return pw_dequant(q, step);
     else return (T)q * ebx2;
+}
+
+// the 32-bit pattern an fp32 or integer output value leaves in the LDS tile
+template <bool PW, typename T>
+__device__ __forceinline__ float tile_val(int q, T ebx2, uint32_t step)
+{
+    if constexpr (std::is_integral_v<T>) return __int_as_float(q);
+    else return dequant<PW>(q, ebx2, step);
 }
 
 template <int CNT, bool VEC4, bool PW, typename T>
 __device__ __forceinline__ void store_run(T* __restrict__ p, const int* q, T ebx2, uint32_t step)
 {
-    if constexpr (VEC4 && sizeof(T) == 4) {
+    if constexpr (VEC4 && std::is_integral_v<T>) {
+#pragma unroll
+        for (int j = 0; j < CNT / 4; j++)
+            *reinterpret_cast<int4*>(p + 4 * j) = make_int4(q[4 * j], q[4 * j + 1], q[4 * j + 2], q[4 * j + 3]);
+    } else if constexpr (VEC4 && sizeof(T) == 4) {
 #pragma unroll
         for (int j = 0; j < CNT / 4; j++)
             *reinterpret_cast<float4*>(p + 4 * j) =
@@ -142,7 +160,7 @@ __device__ __forceinline__ int run_slot(int i) { return i + 4 * (i >> 5); }
 // of whole lines, streamed out.  Values 1024 r .. 1024 r + 1023 start at byte
 // r * row_bytes from `base`: the step's second row in 2-D, 4096 in 1-D (one
 // contiguous run).
-__device__ __forceinline__ void store_tile_runs(const float* tile, float* base, uint32_t row_bytes, int lane)
+__device__ __forceinline__ void store_tile_runs(const float* tile, void* base, uint32_t row_bytes, int lane)
 {
     __syncthreads();  // one wave: orders the tile's writes before its reads
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, -1, kBufferFlags);
@@ -161,12 +179,14 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                                  uint32_t* d_err, int64_t c, int lane, float* tile)
 {
     constexpr bool F64 = sizeof(T) == 8;
-    const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0);
+    constexpr bool INT = std::is_integral_v<T>;
+    const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0, INT ? 1 : 0);
     if (hdr_err) {
         if (c == 0 && lane == 0 && d_err) atomicCAS(d_err, 0u, hdr_err);
         return;
     }
-    const T ebx2 = F64 ? (T)*reinterpret_cast<const double*>(s + kOffEbx2F64)
+    const T ebx2 = INT ? (T)1
+                 : F64 ? (T)*reinterpret_cast<const double*>(s + kOffEbx2F64)
                        : (T)*reinterpret_cast<const float*>(s + kOffEbx2);
     const uint32_t step = PW ? (uint32_t)ebx2 : 0u;  // the point-wise mode's step (checked by check_header)
     const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
@@ -310,11 +330,11 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     for (int r = 0; r < 4; r++) {
                         float* t = tile + (4 * py + r) * kTilePitch + 8 * px;
                         *reinterpret_cast<float4*>(t) =
-                            make_float4(dequant<PW>(d[8 * r], ebx2, step), dequant<PW>(d[8 * r + 1], ebx2, step),
-                                        dequant<PW>(d[8 * r + 2], ebx2, step), dequant<PW>(d[8 * r + 3], ebx2, step));
+                            make_float4(tile_val<PW, T>(d[8 * r], ebx2, step), tile_val<PW, T>(d[8 * r + 1], ebx2, step),
+                                        tile_val<PW, T>(d[8 * r + 2], ebx2, step), tile_val<PW, T>(d[8 * r + 3], ebx2, step));
                         *reinterpret_cast<float4*>(t + 4) =
-                            make_float4(dequant<PW>(d[8 * r + 4], ebx2, step), dequant<PW>(d[8 * r + 5], ebx2, step),
-                                        dequant<PW>(d[8 * r + 6], ebx2, step), dequant<PW>(d[8 * r + 7], ebx2, step));
+                            make_float4(tile_val<PW, T>(d[8 * r + 4], ebx2, step), tile_val<PW, T>(d[8 * r + 5], ebx2, step),
+                                        tile_val<PW, T>(d[8 * r + 6], ebx2, step), tile_val<PW, T>(d[8 * r + 7], ebx2, step));
                     }
                     __syncthreads();  // one wave: orders the tile's writes before its reads
                     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -366,8 +386,8 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                         for (int j = 0; j < 4; j++) {
                             const int* q = d + 16 * r + 4 * j;
                             *reinterpret_cast<float4*>(tile + run_slot(1024 * r + 16 * lane + 4 * j)) =
-                                make_float4(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step),
-                                            dequant<PW>(q[2], ebx2, step), dequant<PW>(q[3], ebx2, step));
+                                make_float4(tile_val<PW, T>(q[0], ebx2, step), tile_val<PW, T>(q[1], ebx2, step),
+                                            tile_val<PW, T>(q[2], ebx2, step), tile_val<PW, T>(q[3], ebx2, step));
                         }
                     // row offsets stay below 2^32: the contiguous extent is below 2^25
                     store_tile_runs(tile, y + (yy * g.n[1] + org[1]), 4u * (uint32_t)g.n[1], lane);
@@ -392,8 +412,8 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     for (int j = 0; j < 8; j++) {
                         const int* q = d + 4 * j;
                         *reinterpret_cast<float4*>(tile + run_slot(32 * lane + 4 * j)) =
-                            make_float4(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step),
-                                        dequant<PW>(q[2], ebx2, step), dequant<PW>(q[3], ebx2, step));
+                            make_float4(tile_val<PW, T>(q[0], ebx2, step), tile_val<PW, T>(q[1], ebx2, step),
+                                        tile_val<PW, T>(q[2], ebx2, step), tile_val<PW, T>(q[3], ebx2, step));
                     }
                     store_tile_runs(tile, y + (org[0] + (int64_t)kStepCodes * st), 4096u, lane);
                 } else {
@@ -414,8 +434,10 @@ template <int RANK, bool VEC4, typename T>
 __device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, T* __restrict__ y,
                                                      const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
 {
-    if constexpr (sizeof(T) == 8) {
-        decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);  // fp64: grid modes only
+    if constexpr (sizeof(T) == 8 || std::is_integral_v<T>) {
+        // fp64 (grid modes only), or the integers of a field-global stream
+        // (dequantized after the carries, in any mode)
+        decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);
     } else {
         if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true, T>(s, y, g, d_err, c, lane, tile);
         else decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);

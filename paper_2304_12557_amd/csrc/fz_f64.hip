@@ -179,15 +179,22 @@ __global__ __launch_bounds__(kF64Threads) void k_prequant64(const double* __rest
     }
 }
 
-// The pre_status of k_compress must see this pass's errors: a second tiny
+// The pre_status of k_compress must see the errors of a pass that wrote the
+// integers (fp64 prequantization, the field-global faces): a second tiny
 // kernel copies the header's status there (a failed block cannot know that
 // the others finished).
-__global__ void k_prequant64_status(uint8_t* __restrict__ out, Geom g)
+__global__ void k_pre_status(uint8_t* __restrict__ out, Geom g)
 {
     if (threadIdx.x == 0) {
         const uint32_t st = *reinterpret_cast<const uint32_t*>(out + kOffStatus);
         if (st) reinterpret_cast<Scratch*>(out + g.scratch_off)->pre_status = st;
     }
+}
+
+hipError_t launch_pre_status(uint8_t* out, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pre_status, dim3(1), dim3(64), 0, st, out, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mode, double eb, hipStream_t st)
@@ -206,8 +213,7 @@ hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mo
     blocks = blocks < 1 ? 1 : blocks > 4096 ? 4096 : blocks;
     hipLaunchKernelGGL(k_prequant64, dim3((unsigned)blocks), dim3(kF64Threads), 0, st, x, n, out, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prequant64_status, dim3(1), dim3(64), 0, st, out, g);
-    return hipGetLastError();
+    return launch_pre_status(out, g, st);
 }
 
 // ------------------------------------------------------------ decompression

@@ -48,6 +48,8 @@ constexpr int kOffMagic = 0, kOffVersion = 4, kOffHdrBytes = 6, kOffStatus = 8, 
               kOffVmax = 60, kOffChunk = 64, kOffNChunks = 72, kOffNnz = 80, kOffNout = 88, kOffTotal = 96;
 // fp64 streams (dtype 1): 2 eb_abs and its reciprocal as doubles (zero in fp32 streams)
 constexpr int kOffEbx2F64 = 104, kOffInvF64 = 112;
+// byte 15: the Lorenzo predictor, 0 inside each chunk, 1 over the whole field
+constexpr int kOffPredictor = 15;
 
 // status bits
 constexpr uint32_t kErrNonfinite = 1u, kErrEbRange = 2u, kErrOutlierCap = 4u;

@@ -21,6 +21,18 @@ hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, con
                                double eb, hipStream_t st);
 hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mode, double eb, hipStream_t st);
 hipError_t launch_decompress_f64(const uint8_t* s, double* y, const Geom& g, uint32_t* d_err, hipStream_t st);
+// copy the header's status to the scratch's pre_status (after a pass that
+// wrote the integer buffer)
+hipError_t launch_pre_status(uint8_t* out, const Geom& g, hipStream_t st);
+// field-global Lorenzo predictor: compression (any fp32 mode) and
+// decompression with its carry passes, which need global_work_bytes(g) of
+// device memory at `work`
+hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
+                                  double eb, hipStream_t st);
+hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t st);
+hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, void* work,
+                                    hipStream_t st);
+size_t global_work_bytes(const Geom& g);
 
 // blocks of the REL range pass of a field of n values
 int64_t minmax_blocks(int64_t n);

@@ -56,6 +56,10 @@ def test_argument_errors_return_immediately():
     assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), float("inf"), 0, ctypes.c_void_p(16), None) == 1
     assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), 1e-310, 0, ctypes.c_void_p(16), None) == 4
     assert L.fz_decompress_f64(None, ctypes.c_void_p(16), ctypes.byref(d), None, None) == 1
+    # field-global predictor: the chunk-local checks, and a work buffer is required
+    assert L.fz_compress_global(ctypes.c_void_p(16), ctypes.byref(d), -1.0, 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress_global(ctypes.c_void_p(16), ctypes.byref(d), 1e-8, 2, ctypes.c_void_p(16), None) == 4
+    assert L.fz_decompress_global(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.byref(d), None, None, None) == 1
     bad = fz.FzDims()
     bad.rank = 4
     assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(bad), 1e-3, 1, ctypes.c_void_p(16), None) == 1
@@ -184,3 +188,15 @@ def test_f64_bound(shape):
     n = int(np.prod(shape))
     b32, b64 = fz.compress_bound(shape), fz.compress_bound(shape, f64=True)
     assert b64 >= b32 + 4 * n and b64 % 4 == 0
+
+
+@pytest.mark.parametrize("shape", [(1,), (70001,), (45, 1030), (20, 40, 70), (512, 512, 512)])
+def test_global_sizes(shape):
+    """The field-global predictor's output buffer holds the fp32 one plus the
+    integers; its decompression work holds one u32 per chunk-box segment of
+    every line along the axis with the most segments."""
+    n = int(np.prod(shape))
+    assert fz.compress_bound(shape, global_lorenzo=True) >= fz.compress_bound(shape) + 4 * n
+    box = {1: (32768,), 2: (32, 1024), 3: (16, 32, 64)}[len(shape)]
+    most = max(4 * (n // shape[a]) * -(-shape[a] // box[a]) for a in range(len(shape)))
+    assert fz.lib().fz_decompress_global_work_bytes(ctypes.byref(fz.dims_of(shape))) == most
