@@ -13,6 +13,7 @@ compression ratio, the roofline of the dominant kernel (HIP events on the
 stream the kernels run on) and the oracle timed on the host cores are added.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -476,6 +477,49 @@ def fp64_input(xt, shape, eb, stream, reps):
     return out
 
 
+def global_predictor(fields, stream, reps):
+    """The field-global Lorenzo predictor against the chunk-local one: ratio
+    and compress / decompress rates (HIP events) per (name, tensor, REL eb)."""
+    import numpy as np
+    import torch
+
+    import paper_2304_12557_amd as fz
+
+    rows = []
+    for name, xt, eb in fields:
+        shape = tuple(xt.shape)
+        in_bytes = 4 * xt.numel()
+        row = {"field": name, "eb": eb}
+        for key, glob in (("chunk_local", False), ("field_global", True)):
+            buf = torch.empty(fz.compress_bound(shape, global_lorenzo=glob), dtype=torch.uint8, device=xt.device)
+            y = torch.empty_like(xt)
+            work = None
+            if glob:
+                nwork = int(fz.lib().fz_decompress_global_work_bytes(ctypes.byref(fz.dims_of(shape))))
+                work = torch.empty(nwork, dtype=torch.uint8, device=xt.device)
+            fz.compress(xt, eb, "rel", out=buf, global_lorenzo=glob)
+            fz.decompress(buf, shape, out=y, global_lorenzo=glob, work=work)
+            torch.cuda.synchronize()
+            info = fz.stream_info(buf)
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+            for k in range(reps):
+                ev[k][0].record(stream)
+                fz.compress(xt, eb, "rel", out=buf, global_lorenzo=glob)
+                ev[k][1].record(stream)
+                fz.decompress(buf, shape, out=y, global_lorenzo=glob, work=work)
+                ev[k][2].record(stream)
+            torch.cuda.synchronize()
+            tc = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+            td = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+            row[key] = {"ratio": round(in_bytes / int(info["total_bytes"]), 3),
+                        "compress_GBps": round(in_bytes / 1e9 / (tc * 1e-3), 2),
+                        "decompress_GBps": round(in_bytes / 1e9 / (td * 1e-3), 2)}
+            del buf, y, work
+        rows.append(row)
+    torch.cuda.empty_cache()
+    return rows
+
+
 def overall_throughput(xt, shape, eb, s_bytes, t_compr_gbps, steps):
     """Overall data-transfer throughput (Sec. 4.6): compress on the device,
     then move the stream to pinned host memory.  Reports the measured
@@ -666,6 +710,10 @@ def main():
                                                        a.steps)
         out["pointwise_relative"] = pointwise_relative(xt, shape, stream, a.steps)
         out["fp64_input"] = fp64_input(xt, shape, a.eb, stream, a.steps)
+        hur = torch.from_numpy(synth.hurricane3d()).to(dev)
+        out["global_predictor"] = global_predictor([("lognormal3d %d^3" % a.n, xt, a.eb),
+                                                    ("hurricane3d 100x500x500", hur, 1e-3)], stream, a.steps)
+        del hur
     if not a.no_ablation:
         out["ablation"] = bench_ablation(xt, float(info["inv"]), tca)
     if not a.no_layers:

@@ -48,7 +48,25 @@ __device__ __forceinline__ int32_t quant_one(float v, const Quant& z, uint32_t& 
     return (int32_t)__builtin_rintf(p);
 }
 
-template <int RANK>
+// 64-bit integer division is a long software sequence on the GPU: the
+// element loops below index with 32-bit integers whenever the field allows
+template <typename I>
+__device__ __forceinline__ void cell_of(int64_t i, const Geom& g, int64_t (&c)[3])
+{
+    const I ii = (I)i, n2 = (I)g.n[2], n1 = (I)g.n[1];
+    const I r = ii / n2;
+    c[2] = (int64_t)(ii - r * n2);
+    c[1] = (int64_t)(r % n1);
+    c[0] = (int64_t)(r / n1);
+}
+
+template <typename I>
+__device__ __forceinline__ int64_t plane_before(int64_t c, int box)
+{
+    return (int64_t)(((I)c / (I)box) * (I)box) - 1;
+}
+
+template <int RANK, typename I>
 __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict__ x, uint8_t* __restrict__ out,
                                                          Geom g)
 {
@@ -62,12 +80,10 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
     uint32_t err = 0;
     for (int64_t i = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; i < n; i += stride) {
         int64_t c[3];
-        c[2] = i % g.n[2];
-        c[1] = (i / g.n[2]) % g.n[1];
-        c[0] = i / (g.n[2] * g.n[1]);
+        cell_of<I>(i, g, c);
         int64_t lo[3];  // the plane just before the chunk along each axis (-1: outside the field)
 #pragma unroll
-        for (int a = 0; a < 3; a++) lo[a] = (c[a] / g.box[a]) * g.box[a] - 1;
+        for (int a = 0; a < 3; a++) lo[a] = a < RANK ? plane_before<I>(c[a], g.box[a]) : -1;
         uint32_t acc = 0;
         uint32_t dummy = 0;
         // subsets of the axes the rank has (axes 0 .. RANK-1; the others
@@ -112,10 +128,14 @@ hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t 
     const int64_t n = g.n[0] * g.n[1] * g.n[2];
     int64_t blocks = (n + kGlobalThreads - 1) / kGlobalThreads;
     blocks = blocks < 1 ? 1 : blocks > 8192 ? 8192 : blocks;
-    switch (g.rank) {
-        case 3: hipLaunchKernelGGL(k_face<3>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 2: hipLaunchKernelGGL(k_face<2>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        default: hipLaunchKernelGGL(k_face<1>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+    const bool small = n < (1ll << 32);
+    switch (g.rank * 2 + (small ? 1 : 0)) {
+        case 7: hipLaunchKernelGGL((k_face<3, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 6: hipLaunchKernelGGL((k_face<3, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 5: hipLaunchKernelGGL((k_face<2, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 4: hipLaunchKernelGGL((k_face<2, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 3: hipLaunchKernelGGL((k_face<1, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        default: hipLaunchKernelGGL((k_face<1, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -151,7 +171,7 @@ __host__ __device__ inline Lines lines_of(const Geom& g, int ax)
     return l;
 }
 
-// carry[line][j] = sum of the values at the ends of segments 0 .. j-1 of the line
+// carry[j][line] = sum of the values at the ends of segments 0 .. j-1 of the line
 __global__ __launch_bounds__(kGlobalThreads) void k_seg_carry(const uint32_t* __restrict__ f, uint32_t* __restrict__ carry,
                                                               Lines l)
 {
@@ -160,10 +180,9 @@ __global__ __launch_bounds__(kGlobalThreads) void k_seg_carry(const uint32_t* __
     for (int64_t t = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; t < nlines; t += stride) {
         const int64_t a = t / l.B, b = t % l.B;
         const uint32_t* line = f + a * l.L * l.B + b;
-        uint32_t* cl = carry + t * l.nseg;
         uint32_t run = 0;
         for (int64_t j = 0; j < l.nseg; j++) {
-            cl[j] = run;
+            carry[j * nlines + t] = run;
             const int64_t end = (j + 1) * l.seg < l.L ? (j + 1) * l.seg - 1 : l.L - 1;
             run += line[end * l.B];
         }
@@ -172,10 +191,11 @@ __global__ __launch_bounds__(kGlobalThreads) void k_seg_carry(const uint32_t* __
 
 // f += carry of its segment; on the last axis also dequantize (Sec. 2.3; the
 // point-wise mode's inverse transform) and store the fp32 value in place
-template <bool LAST>
+template <bool LAST, typename I>
 __global__ __launch_bounds__(kGlobalThreads) void k_seg_add(uint32_t* __restrict__ f, const uint32_t* __restrict__ carry,
                                                             Lines l, const uint8_t* __restrict__ s)
 {
+    const I B = (I)l.B, L = (I)l.L, seg = (I)l.seg, nlines = (I)(l.A * l.B);
     const int64_t n = l.A * l.L * l.B;
     const int64_t stride = (int64_t)gridDim.x * kGlobalThreads;
     float ebx2 = 0.0f;
@@ -187,9 +207,10 @@ __global__ __launch_bounds__(kGlobalThreads) void k_seg_add(uint32_t* __restrict
         step = pw ? (uint32_t)ebx2 : 0u;
     }
     for (int64_t i = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; i < n; i += stride) {
-        const int64_t b = i % l.B, r = i / l.B;
-        const int64_t k = r % l.L, a = r / l.L;
-        const uint32_t v = f[i] + carry[(a * l.B + b) * l.nseg + k / l.seg];
+        const I ii = (I)i;
+        const I r = ii / B, b = ii - r * B;
+        const I a = r / L, k = r - a * L;
+        const uint32_t v = f[i] + carry[(int64_t)(k / seg) * (int64_t)nlines + (int64_t)(a * B + b)];
         if (LAST) {
             const int q = (int)v;
             f[i] = __float_as_uint(pw ? pw_dequant(q, step) : (float)q * ebx2);
@@ -256,10 +277,15 @@ hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, u
         if ((e = hipGetLastError()) != hipSuccess) return e;
         int64_t ba = (n + kGlobalThreads - 1) / kGlobalThreads;
         ba = ba < 1 ? 1 : ba > 8192 ? 8192 : ba;
-        if (ax == 0)
-            hipLaunchKernelGGL(k_seg_add<true>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
+        const bool small = n < (1ll << 32);
+        if (ax == 0 && small)
+            hipLaunchKernelGGL((k_seg_add<true, uint32_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
+        else if (ax == 0)
+            hipLaunchKernelGGL((k_seg_add<true, uint64_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
+        else if (small)
+            hipLaunchKernelGGL((k_seg_add<false, uint32_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
         else
-            hipLaunchKernelGGL(k_seg_add<false>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
+            hipLaunchKernelGGL((k_seg_add<false, uint64_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
