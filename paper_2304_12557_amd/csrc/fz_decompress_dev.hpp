@@ -174,6 +174,35 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, u
     __syncthreads();  // the tile is rewritten by the next step
 }
 
+// The fp64 output's tiles (twice the words; the caller's LDS holds
+// kTileFloats64 floats): 3-D rows of 64 doubles with a pitch of 68 doubles;
+// 2-D and 1-D runs of the step's 2048 doubles with 2 doubles of padding after
+// every 16.  Every store instruction writes whole 512-byte rows (3-D) or
+// 1 KiB of one row (2-D, 1-D), streamed out.
+constexpr int kTilePitch64 = 68;  // doubles
+constexpr int kTileFloats64 = 2 * (2048 + 2 * (2048 / 16));
+static_assert(2 * 32 * kTilePitch64 <= kTileFloats64, "the 3-D fp64 tile fits");
+__device__ __forceinline__ int run_slot64(int i) { return i + 2 * (i >> 4); }
+
+__device__ __forceinline__ void store_nt2(double* p, double a, double b)
+{
+    const fz_f64x2 v = {a, b};
+    __builtin_nontemporal_store(v, reinterpret_cast<fz_f64x2*>(p));
+}
+
+// 2-D / 1-D: instruction i writes doubles 128 i .. 128 i + 127 of the step;
+// doubles 1024 r .. start at element r * row_elems from `base`
+__device__ __forceinline__ void store_tile_runs64(const double* tile, double* base, int64_t row_elems, int lane)
+{
+    __syncthreads();  // one wave: orders the tile's writes before its reads
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const double2 v = *reinterpret_cast<const double2*>(tile + run_slot64(128 * i + 2 * lane));
+        store_nt2(base + (int64_t)(i >> 3) * row_elems + 128 * (i & 7) + 2 * lane, v.x, v.y);
+    }
+    __syncthreads();  // the tile is rewritten by the next step
+}
+
 template <int RANK, bool VEC4, bool PW, typename T>
 __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, T* __restrict__ y, const Geom& g,
                                                  uint32_t* d_err, int64_t c, int lane, float* tile)
@@ -351,6 +380,27 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                                                kCacheStream);
                     }
                     __syncthreads();  // the tile is rewritten by the next step
+                } else if constexpr (VEC4 && F64) {
+                    // through LDS as above: every store writes 2 whole rows of 64 doubles
+                    double* t64 = reinterpret_cast<double*>(tile);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        double* t = t64 + (4 * py + r) * kTilePitch64 + 8 * px;
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            *reinterpret_cast<double2*>(t + 2 * j) =
+                                make_double2(dequant<PW>(d[8 * r + 2 * j], ebx2, step),
+                                             dequant<PW>(d[8 * r + 2 * j + 1], ebx2, step));
+                    }
+                    __syncthreads();  // one wave: orders the tile's writes before its reads
+                    T* base = y + (z * g.n[1] + org[1]) * g.n[2] + org[2];
+#pragma unroll
+                    for (int i = 0; i < 16; i++) {
+                        const int row = 2 * i + (lane >> 5), col = 2 * (lane & 31);
+                        const double2 v = *reinterpret_cast<const double2*>(t64 + row * kTilePitch64 + col);
+                        store_nt2(base + (int64_t)row * g.n[2] + col, v.x, v.y);
+                    }
+                    __syncthreads();  // the tile is rewritten by the next step
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; r++) store_run<8, VEC4, PW>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, step);
@@ -391,6 +441,17 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                         }
                     // row offsets stay below 2^32: the contiguous extent is below 2^25
                     store_tile_runs(tile, y + (yy * g.n[1] + org[1]), 4u * (uint32_t)g.n[1], lane);
+                } else if constexpr (VEC4 && F64) {
+                    double* t64 = reinterpret_cast<double*>(tile);
+#pragma unroll
+                    for (int r = 0; r < 2; r++)
+#pragma unroll
+                        for (int j = 0; j < 8; j++) {
+                            const int* q = d + 16 * r + 2 * j;
+                            *reinterpret_cast<double2*>(t64 + run_slot64(1024 * r + 16 * lane + 2 * j)) =
+                                make_double2(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step));
+                        }
+                    store_tile_runs64(t64, y + (yy * g.n[1] + org[1]), g.n[1], lane);
                 } else {
                     store_run<16, VEC4, PW>(y + (yy * g.n[1] + x0), d, ebx2, step);
                     store_run<16, VEC4, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step);
@@ -416,6 +477,15 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                         tile_val<PW, T>(q[2], ebx2, step), tile_val<PW, T>(q[3], ebx2, step));
                     }
                     store_tile_runs(tile, y + (org[0] + (int64_t)kStepCodes * st), 4096u, lane);
+                } else if constexpr (VEC4 && F64) {
+                    double* t64 = reinterpret_cast<double*>(tile);
+#pragma unroll
+                    for (int j = 0; j < 16; j++) {
+                        const int* q = d + 2 * j;
+                        *reinterpret_cast<double2*>(t64 + run_slot64(32 * lane + 2 * j)) =
+                            make_double2(dequant<PW>(q[0], ebx2, step), dequant<PW>(q[1], ebx2, step));
+                    }
+                    store_tile_runs64(t64, y + (org[0] + (int64_t)kStepCodes * st), 1024, lane);
                 } else {
                     store_run<32, VEC4, PW>(y + x0, d, ebx2, step);
                 }

@@ -14,6 +14,7 @@ namespace fz {
 constexpr int kBufferFlags = 0x00020000;
 typedef uint32_t fz_u32x4 __attribute__((ext_vector_type(4)));
 typedef float fz_f32x4 __attribute__((ext_vector_type(4)));
+typedef double fz_f64x2 __attribute__((ext_vector_type(2)));
 
 // cache policy of a buffer access: nontemporal (the nt bit).  Used where a
 // kernel streams data it never touches again -- the reconstructed field,

@@ -17,7 +17,6 @@
 namespace fz {
 
 constexpr int kF64Threads = 256;
-typedef double fz_f64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ bool finite64(double v) { return __builtin_fabs(v) <= 1.7976931348623157e308; }
 
@@ -221,7 +220,7 @@ template <int RANK, bool VEC4>
 __global__ __launch_bounds__(64) void k_decompress64(const uint8_t* __restrict__ s, double* __restrict__ y, Geom g,
                                                      uint32_t* d_err)
 {
-    __shared__ float tile[kTileFloats];
+    __shared__ __attribute__((aligned(16))) float tile[kTileFloats64];
     decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 

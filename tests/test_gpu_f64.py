@@ -70,6 +70,8 @@ def check(x, eb, mode, threads=1, misalign=False):
     ((33, 65, 131), 1e-3, O.EB_REL),   # box + 1, contiguous extent odd
     ((45, 1030), 1e-3, O.EB_ABS),      # 2-D ragged
     ((33, 1027), 1e-4, O.EB_REL),      # 2-D, contiguous extent not a multiple of 4
+    ((70, 2052), 1e-4, O.EB_REL),      # 2-D, 3 x 3 chunks, whole rows through the LDS tile
+    ((40, 70, 128), 1e-3, O.EB_ABS),   # 3-D, interior chunks through the LDS tile
     ((70001,), 1e-5, O.EB_REL),        # 1-D ragged
     ((65537,), 1e-3, O.EB_ABS),        # 1-D, two chunks and one value
     ((1,), 1e-3, O.EB_REL), ((3, 1, 5), 1e-3, O.EB_ABS),
