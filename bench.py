@@ -397,6 +397,32 @@ def rate_distortion(xt, shape):
     return rows
 
 
+def hbm_reference(xt, y, stream, reps):
+    """What plain streaming kernels reach on the same buffers (HIP events):
+    a fill of the output (writes only, the decompressor's dominant traffic)
+    and an elementwise copy (reads and writes).  Context for the roofline
+    fractions, which are taken against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+
+    def timed(fn):
+        fn()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+        for k in range(reps):
+            ev[k][0].record(stream)
+            fn()
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+
+    nbytes = 4 * xt.numel()
+    t_fill = timed(lambda: y.fill_(1.0))
+    t_copy = timed(lambda: y.copy_(xt))
+    return {"fill_GBps": round(nbytes / 1e9 / (t_fill * 1e-3), 1),
+            "copy_GBps": round(2 * nbytes / 1e9 / (t_copy * 1e-3), 1),
+            "note": "torch fill_ (4 B written per value) and copy_ (4 B read + 4 B written) of the benchmark field"}
+
+
 def pointwise_relative(xt, shape, stream, reps):
     """The point-wise relative mode on the same field: compress and
     decompress time (HIP events), ratio, and the largest |x' - x| /
@@ -704,6 +730,7 @@ def main():
                      "traffic": measured_traffic(name, shape, a.eb),
                      "algorithmic_bytes": int(alg), "avg_launch_ms": round(t_ms, 4)},
     }
+    out["hbm_reference"] = hbm_reference(xt, y, stream, a.steps)
     if not a.no_quality:
         out["rate_distortion"] = rate_distortion(xt, shape)
         out["overall_throughput"] = overall_throughput(xt, shape, a.eb, s_bytes, in_bytes / 1e9 / (tc * 1e-3),
