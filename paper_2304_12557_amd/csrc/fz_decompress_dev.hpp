@@ -169,7 +169,7 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, u
         const float4 v = *reinterpret_cast<const float4*>(tile + run_slot(256 * i + 4 * lane));
         const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
         const uint32_t soff = (uint32_t)(i >> 2) * row_bytes + 1024u * (uint32_t)(i & 3);
-        __builtin_amdgcn_raw_buffer_store_b128(w, rs, 16u * (uint32_t)lane, soff, kCacheStream);
+        __builtin_amdgcn_raw_buffer_store_b128(w, rs, 16u * (uint32_t)lane, soff, kCacheStreamStore);
     }
     __syncthreads();  // the tile is rewritten by the next step
 }
@@ -377,7 +377,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                         const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
                                             __float_as_uint(v.w)};
                         __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2],
-                                                               kCacheStream);
+                                                               kCacheStreamStore);
                     }
                     __syncthreads();  // the tile is rewritten by the next step
                 } else if constexpr (VEC4 && F64) {

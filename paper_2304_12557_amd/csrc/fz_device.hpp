@@ -24,6 +24,11 @@ typedef double fz_f64x2 __attribute__((ext_vector_type(2)));
 // 128-byte lines per instruction: partial-line nontemporal stores lose the
 // merging in L2 (measured 3-6x slower).
 constexpr int kCacheStream = 2;
+// the same for whole-line stores of data no kernel of the pipeline reads back
+// soon (the reconstructed field): nt with system scope (sc1), which measured
+// 116 -> 112 us against nt alone for back-to-back 512^3 decompressions (after
+// a compression the two are within noise)
+constexpr int kCacheStreamStore = 2 | 16;
 
 // lane l receives lane l-1's value (DPP wave_shr:1).  Lane 0 receives an
 // unspecified value: the compiler may leave the DPP destination of a lane
