@@ -182,10 +182,10 @@ int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, 
  * fz_compress_global: as fz_compress, with the same arguments and errors.
  * fz_decompress_global_work_bytes: device scratch fz_decompress_global needs
  * (one u32 carry per chunk-box segment of every line along each axis: about
- * N/4 bytes for a 3-D field); 0 on invalid dims.
+ * 0.44 N bytes for a 3-D field); 0 on invalid dims.
  * fz_decompress_global: as fz_decompress, plus d_work (that many bytes,
- * device, overwritten).  It writes d_out in several passes (the chunk kernel's
- * local sums, then the carries along each axis), so a rejected stream
+ * device, overwritten).  It writes d_out twice (the chunk kernel's local
+ * sums, then the values with every axis's carries), so a rejected stream
  * (*d_err set) leaves d_out unspecified.  fz_decompress and the batch layer
  * reject field-global streams (FZ_ERR_STREAM), and fz_decompress_global
  * rejects chunk-local ones. */

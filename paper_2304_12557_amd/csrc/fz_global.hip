@@ -16,11 +16,10 @@
 //
 // Decompression runs the chunk kernel with integer output, which yields the
 // chunk-local prefix sums p again, and then turns them into the field-global
-// prefix sums q one axis at a time: along an axis the global sum of a
-// segment is its local sum plus the sum of the totals of the segments before
-// it, so per axis k_seg_carry scans the segment-end values of every line
-// into a carry per segment and k_seg_add adds it (the last axis also
-// dequantizes).  Wrapping 32-bit integer arithmetic throughout.
+// prefix sums q: per axis a small kernel computes the carries of every line's
+// segments from the segment-end values (k_seg_carry), and one pass adds them
+// all and dequantizes (k_seg_final).  Wrapping 32-bit integer arithmetic
+// throughout.
 #include <hip/hip_runtime.h>
 
 #include "fz.h"
@@ -151,72 +150,114 @@ __global__ __launch_bounds__(64) void k_decompress_int(const uint8_t* __restrict
     decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
-// The field as (A, L, B) around axis `ax` (A = product of the extents before
-// it, L its extent, B the product after it); a line is one (a, b) pair and
-// its segments are the chunk box's runs along the axis.
-struct Lines {
-    int64_t A, L, B, seg, nseg;
+// Carries of the field-global prefix sums.  Along axis ax the field splits
+// into lines (every cell with the other coordinates fixed) and each line into
+// segments of the chunk box's extent along ax (a power of two).  After the
+// chunk kernel the field holds p, the chunk-local sums.  Taking the axes from
+// the contiguous one to the slowest, the global sum along an axis of a value
+// that already holds the earlier axes' carries is its local sum plus the
+// totals of the line's earlier segments; those totals are the values at the
+// segment ends, which are p plus the earlier axes' carries there.  So per axis
+// one small kernel reads only the segment ends and writes the carries
+// (carry[ax][j][line] = sum over the segments before j), and one final pass
+// adds every axis's carry to p and dequantizes.  The sums commute, and all of
+// it is wrapping 32-bit arithmetic.
+struct Carries {
+    int rank;
+    int64_t n[3];
+    int sh[3];          // log2 of the chunk box along each axis
+    int64_t nlines[3];  // lines along each axis
+    int64_t nseg[3];    // segments per line
+    int64_t off[3];     // start of each axis's carries in the work buffer (u32 units)
 };
 
-__host__ __device__ inline Lines lines_of(const Geom& g, int ax)
+inline Carries carries_of(const Geom& g)
 {
-    Lines l;
-    l.A = 1;
-    l.B = 1;
-    for (int i = 0; i < ax; i++) l.A *= g.n[i];
-    for (int i = ax + 1; i < 3; i++) l.B *= g.n[i];
-    l.L = g.n[ax];
-    l.seg = g.box[ax];
-    l.nseg = (l.L + l.seg - 1) / l.seg;
-    return l;
+    Carries c;
+    c.rank = g.rank;
+    int64_t off = 0;
+    for (int a = 0; a < 3; a++) {
+        c.n[a] = g.n[a];
+        c.sh[a] = __builtin_ctz((unsigned)g.box[a]);
+        c.nlines[a] = g.n[0] * g.n[1] * g.n[2] / g.n[a];
+        c.nseg[a] = (g.n[a] + g.box[a] - 1) / g.box[a];
+        c.off[a] = off;
+        if (a < g.rank) off += c.nlines[a] * c.nseg[a];
+    }
+    return c;
 }
 
-// carry[j][line] = sum of the values at the ends of segments 0 .. j-1 of the line
-__global__ __launch_bounds__(kGlobalThreads) void k_seg_carry(const uint32_t* __restrict__ f, uint32_t* __restrict__ carry,
-                                                              Lines l)
+// the line of axis ax through cell (c0, c1, c2)
+__device__ __forceinline__ int64_t line_of(const Carries& k, int ax, int64_t c0, int64_t c1, int64_t c2)
 {
-    const int64_t nlines = l.A * l.B;
+    return ax == 2 ? c0 * k.n[1] + c1 : ax == 1 ? c0 * k.n[2] + c2 : c1 * k.n[2] + c2;
+}
+
+// the sum of the carries of axes first .. rank-1 at cell (c0, c1, c2)
+__device__ __forceinline__ uint32_t carry_sum(const Carries& k, const uint32_t* __restrict__ w, int first, int64_t c0,
+                                              int64_t c1, int64_t c2)
+{
+    uint32_t v = 0;
+    const int64_t c[3] = {c0, c1, c2};
+    for (int ax = first; ax < k.rank; ax++)
+        v += w[k.off[ax] + (c[ax] >> k.sh[ax]) * k.nlines[ax] + line_of(k, ax, c0, c1, c2)];
+    return v;
+}
+
+__global__ __launch_bounds__(kGlobalThreads) void k_seg_carry(const uint32_t* __restrict__ p, uint32_t* __restrict__ w,
+                                                              Carries k, int ax)
+{
+    const int64_t nl = k.nlines[ax];
     const int64_t stride = (int64_t)gridDim.x * kGlobalThreads;
-    for (int64_t t = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; t < nlines; t += stride) {
-        const int64_t a = t / l.B, b = t % l.B;
-        const uint32_t* line = f + a * l.L * l.B + b;
+    for (int64_t t = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; t < nl; t += stride) {
+        // the other two coordinates of line t
+        int64_t c[3];
+        if (ax == 2) { c[0] = t / k.n[1]; c[1] = t % k.n[1]; }
+        else if (ax == 1) { c[0] = t / k.n[2]; c[2] = t % k.n[2]; }
+        else { c[1] = t / k.n[2]; c[2] = t % k.n[2]; }
         uint32_t run = 0;
-        for (int64_t j = 0; j < l.nseg; j++) {
-            carry[j * nlines + t] = run;
-            const int64_t end = (j + 1) * l.seg < l.L ? (j + 1) * l.seg - 1 : l.L - 1;
-            run += line[end * l.B];
+        for (int64_t j = 0; j < k.nseg[ax]; j++) {
+            w[k.off[ax] + j * nl + t] = run;
+            const int64_t end = ((j + 1) << k.sh[ax]) < k.n[ax] ? ((j + 1) << k.sh[ax]) - 1 : k.n[ax] - 1;
+            c[ax] = end;
+            run += p[(c[0] * k.n[1] + c[1]) * k.n[2] + c[2]] + carry_sum(k, w, ax + 1, c[0], c[1], c[2]);
         }
     }
 }
 
-// f += carry of its segment; on the last axis also dequantize (Sec. 2.3; the
-// point-wise mode's inverse transform) and store the fp32 value in place
-template <bool LAST, typename I>
-__global__ __launch_bounds__(kGlobalThreads) void k_seg_add(uint32_t* __restrict__ f, const uint32_t* __restrict__ carry,
-                                                            Lines l, const uint8_t* __restrict__ s)
+// q = p + the carries of every axis, dequantized (Sec. 2.3; the point-wise
+// mode's inverse transform) and stored as fp32 in place.  A block takes 256
+// consecutive cells of one row (the cells that share every coordinate but
+// the contiguous one), so the row's coordinates and carry offsets are
+// uniform and no per-cell division is needed.
+template <int RANK>
+__global__ __launch_bounds__(kGlobalThreads) void k_seg_final(uint32_t* __restrict__ f, const uint32_t* __restrict__ w,
+                                                              Carries k, const uint8_t* __restrict__ s)
 {
-    const I B = (I)l.B, L = (I)l.L, seg = (I)l.seg, nlines = (I)(l.A * l.B);
-    const int64_t n = l.A * l.L * l.B;
-    const int64_t stride = (int64_t)gridDim.x * kGlobalThreads;
-    float ebx2 = 0.0f;
-    uint32_t step = 0;
-    bool pw = false;
-    if (LAST) {
-        ebx2 = *reinterpret_cast<const float*>(s + kOffEbx2);
-        pw = s[kOffEbMode] == 2;
-        step = pw ? (uint32_t)ebx2 : 0u;
-    }
-    for (int64_t i = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; i < n; i += stride) {
-        const I ii = (I)i;
-        const I r = ii / B, b = ii - r * B;
-        const I a = r / L, k = r - a * L;
-        const uint32_t v = f[i] + carry[(int64_t)(k / seg) * (int64_t)nlines + (int64_t)(a * B + b)];
-        if (LAST) {
-            const int q = (int)v;
-            f[i] = __float_as_uint(pw ? pw_dequant(q, step) : (float)q * ebx2);
+    const float ebx2 = *reinterpret_cast<const float*>(s + kOffEbx2);
+    const bool pw = s[kOffEbMode] == 2;
+    const uint32_t step = pw ? (uint32_t)ebx2 : 0u;
+    const int64_t nx = k.n[RANK - 1];
+    const int64_t nxb = (nx + kGlobalThreads - 1) / kGlobalThreads;
+    const int64_t nrows = k.n[0] * k.n[1] * k.n[2] / nx;
+    for (int64_t blk = blockIdx.x; blk < nrows * nxb; blk += gridDim.x) {
+        const int64_t row = blk / nxb;  // uniform
+        const int64_t x = (blk - row * nxb) * kGlobalThreads + threadIdx.x;
+        if (x >= nx) continue;
+        uint32_t c;
+        if constexpr (RANK == 3) {
+            const int64_t c0 = row / k.n[1], c1 = row - c0 * k.n[1];
+            c = w[k.off[2] + (x >> k.sh[2]) * k.nlines[2] + row] +
+                w[k.off[1] + (c1 >> k.sh[1]) * k.nlines[1] + c0 * k.n[2] + x] +
+                w[k.off[0] + (c0 >> k.sh[0]) * k.nlines[0] + c1 * k.n[2] + x];
+        } else if constexpr (RANK == 2) {
+            c = w[k.off[1] + (x >> k.sh[1]) * k.nlines[1] + row] + w[k.off[0] + (row >> k.sh[0]) * k.nlines[0] + x];
         } else {
-            f[i] = v;
+            c = w[k.off[0] + (x >> k.sh[0])];
         }
+        const int64_t i = row * nx + x;
+        const int q = (int)(f[i] + c);
+        f[i] = __float_as_uint(pw ? pw_dequant(q, step) : (float)q * ebx2);
     }
 }
 
@@ -236,13 +277,10 @@ static hipError_t launch_rank_int(const uint8_t* s, int32_t* y, const Geom& g, u
 
 size_t global_work_bytes(const Geom& g)
 {
-    int64_t most = 0;
-    for (int ax = 0; ax < g.rank; ax++) {
-        const Lines l = lines_of(g, ax);
-        const int64_t b = 4 * l.A * l.B * l.nseg;
-        most = b > most ? b : most;
-    }
-    return (size_t)most;
+    const Carries k = carries_of(g);
+    int64_t total = 0;
+    for (int ax = 0; ax < g.rank; ax++) total += k.nlines[ax] * k.nseg[ax];
+    return (size_t)(4 * total);
 }
 
 hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, void* work,
@@ -265,29 +303,24 @@ hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, u
     }
     if (e != hipSuccess) return e;
     uint32_t* f = reinterpret_cast<uint32_t*>(y);
-    uint32_t* carry = static_cast<uint32_t*>(work);
-    // the contiguous axis first, then the middle, then the slowest: the
-    // order of the inclusive sums of the inverse predictor
+    uint32_t* w = static_cast<uint32_t*>(work);
+    const Carries k = carries_of(g);
+    // the contiguous axis first, then the middle, then the slowest
     for (int ax = g.rank - 1; ax >= 0; ax--) {
-        const Lines l = lines_of(g, ax);
-        const int64_t nlines = l.A * l.B, n = l.A * l.L * l.B;
-        int64_t bc = (nlines + kGlobalThreads - 1) / kGlobalThreads;
+        int64_t bc = (k.nlines[ax] + kGlobalThreads - 1) / kGlobalThreads;
         bc = bc < 1 ? 1 : bc > 4096 ? 4096 : bc;
-        hipLaunchKernelGGL(k_seg_carry, dim3((unsigned)bc), dim3(kGlobalThreads), 0, st, f, carry, l);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        int64_t ba = (n + kGlobalThreads - 1) / kGlobalThreads;
-        ba = ba < 1 ? 1 : ba > 8192 ? 8192 : ba;
-        const bool small = n < (1ll << 32);
-        if (ax == 0 && small)
-            hipLaunchKernelGGL((k_seg_add<true, uint32_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
-        else if (ax == 0)
-            hipLaunchKernelGGL((k_seg_add<true, uint64_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
-        else if (small)
-            hipLaunchKernelGGL((k_seg_add<false, uint32_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
-        else
-            hipLaunchKernelGGL((k_seg_add<false, uint64_t>), dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, carry, l, s);
+        hipLaunchKernelGGL(k_seg_carry, dim3((unsigned)bc), dim3(kGlobalThreads), 0, st, f, w, k, ax);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    const int64_t nx = g.n[g.rank - 1];
+    int64_t ba = (g.n[0] * g.n[1] * g.n[2] / nx) * ((nx + kGlobalThreads - 1) / kGlobalThreads);
+    ba = ba < 1 ? 1 : ba > 16384 ? 16384 : ba;
+    switch (g.rank) {
+        case 3: hipLaunchKernelGGL(k_seg_final<3>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+        case 2: hipLaunchKernelGGL(k_seg_final<2>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+        default: hipLaunchKernelGGL(k_seg_final<1>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipSuccess;
 }
 
