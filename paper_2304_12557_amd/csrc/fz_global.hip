@@ -47,25 +47,13 @@ __device__ __forceinline__ int32_t quant_one(float v, const Quant& z, uint32_t& 
     return (int32_t)__builtin_rintf(p);
 }
 
-// 64-bit integer division is a long software sequence on the GPU: the
-// element loops below index with 32-bit integers whenever the field allows
-template <typename I>
-__device__ __forceinline__ void cell_of(int64_t i, const Geom& g, int64_t (&c)[3])
-{
-    const I ii = (I)i, n2 = (I)g.n[2], n1 = (I)g.n[1];
-    const I r = ii / n2;
-    c[2] = (int64_t)(ii - r * n2);
-    c[1] = (int64_t)(r % n1);
-    c[0] = (int64_t)(r / n1);
-}
-
-template <typename I>
-__device__ __forceinline__ int64_t plane_before(int64_t c, int box)
-{
-    return (int64_t)(((I)c / (I)box) * (I)box) - 1;
-}
-
-template <int RANK, typename I>
+// p of one cell from the quantized values q(c) of the cell and of its face
+// neighbours: a block takes 256 consecutive cells of one row (every
+// coordinate but the contiguous one fixed), so the row's coordinates, the
+// planes before the chunk along the slow axes and their row addresses are
+// uniform.  Only the cell's own value reports a status; a face value is
+// another cell's own value.
+template <int RANK>
 __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict__ x, uint8_t* __restrict__ out,
                                                          Geom g)
 {
@@ -74,40 +62,50 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
     if (scr->pre_status) return;  // set before this launch (REL range pass): uniform
     const Quant z = quant_of(out);
     int32_t* p = reinterpret_cast<int32_t*>(out + g.q_off);
-    const int64_t n = g.n[0] * g.n[1] * g.n[2];
-    const int64_t stride = (int64_t)gridDim.x * kGlobalThreads;
-    uint32_t err = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; i < n; i += stride) {
-        int64_t c[3];
-        cell_of<I>(i, g, c);
-        int64_t lo[3];  // the plane just before the chunk along each axis (-1: outside the field)
-#pragma unroll
-        for (int a = 0; a < 3; a++) lo[a] = a < RANK ? plane_before<I>(c[a], g.box[a]) : -1;
-        uint32_t acc = 0;
-        uint32_t dummy = 0;
-        // subsets of the axes the rank has (axes 0 .. RANK-1; the others
-        // have extent 1): bit a of m moves axis a
-#pragma unroll
-        for (int m = 0; m < (1 << RANK); m++) {
-            int64_t q[3] = {c[0], c[1], c[2]};
-            bool ghost = false;
-            int par = 0;
-#pragma unroll
-            for (int a = 0; a < RANK; a++) {
-                if ((m >> a) & 1) {
-                    q[a] = lo[a];
-                    ghost |= lo[a] < 0;
-                    par ^= 1;
+    const int64_t nx = g.n[RANK - 1];
+    const int64_t nxb = (nx + kGlobalThreads - 1) / kGlobalThreads;
+    const int64_t nrows = g.n[0] * g.n[1] * g.n[2] / nx;
+    const int shx = __builtin_ctz((unsigned)g.box[RANK - 1]);  // chunk boxes are powers of two
+    uint32_t err = 0, dummy = 0;
+    auto qv = [&](int64_t idx, bool own) -> uint32_t { return (uint32_t)quant_one(x[idx], z, own ? err : dummy); };
+    for (int64_t blk = blockIdx.x; blk < nrows * nxb; blk += gridDim.x) {
+        const int64_t row = blk / nxb;  // uniform
+        const int64_t c = (blk - row * nxb) * kGlobalThreads + threadIdx.x;
+        if (c >= nx) continue;
+        const int64_t X = ((c >> shx) << shx) - 1;  // the column before the chunk (-1: outside the field)
+        uint32_t acc;
+        if constexpr (RANK == 1) {
+            acc = qv(c, true) - (X >= 0 ? qv(X, false) : 0u);
+        } else if constexpr (RANK == 2) {
+            const int64_t Y = (row / g.box[0]) * g.box[0] - 1;
+            const int64_t r0 = row * nx, rY = Y * nx;
+            acc = qv(r0 + c, true);
+            if (X >= 0) acc -= qv(r0 + X, false);
+            if (Y >= 0) {
+                acc -= qv(rY + c, false);
+                if (X >= 0) acc += qv(rY + X, false);
+            }
+        } else {
+            const int64_t c0 = row / g.n[1], c1 = row - c0 * g.n[1];
+            const int64_t Z = (c0 / g.box[0]) * g.box[0] - 1, Y = (c1 / g.box[1]) * g.box[1] - 1;
+            const int64_t r00 = row * nx, rZ0 = (Z * g.n[1] + c1) * nx, r0Y = (c0 * g.n[1] + Y) * nx,
+                          rZY = (Z * g.n[1] + Y) * nx;
+            acc = qv(r00 + c, true);
+            if (X >= 0) acc -= qv(r00 + X, false);
+            if (Y >= 0) {
+                acc -= qv(r0Y + c, false);
+                if (X >= 0) acc += qv(r0Y + X, false);
+            }
+            if (Z >= 0) {
+                acc -= qv(rZ0 + c, false);
+                if (X >= 0) acc += qv(rZ0 + X, false);
+                if (Y >= 0) {
+                    acc += qv(rZY + c, false);
+                    if (X >= 0) acc -= qv(rZY + X, false);
                 }
             }
-            if (ghost) continue;
-            const float v = x[(q[0] * g.n[1] + q[1]) * g.n[2] + q[2]];
-            // only the cell's own value reports a status; a face value is
-            // another cell's own value
-            const uint32_t t = (uint32_t)quant_one(v, z, m == 0 ? err : dummy);
-            acc = par ? acc - t : acc + t;
         }
-        p[i] = (int32_t)acc;
+        p[row * nx + c] = (int32_t)acc;
     }
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
@@ -124,17 +122,13 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
 
 hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
-    const int64_t n = g.n[0] * g.n[1] * g.n[2];
-    int64_t blocks = (n + kGlobalThreads - 1) / kGlobalThreads;
-    blocks = blocks < 1 ? 1 : blocks > 8192 ? 8192 : blocks;
-    const bool small = n < (1ll << 32);
-    switch (g.rank * 2 + (small ? 1 : 0)) {
-        case 7: hipLaunchKernelGGL((k_face<3, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 6: hipLaunchKernelGGL((k_face<3, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 5: hipLaunchKernelGGL((k_face<2, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 4: hipLaunchKernelGGL((k_face<2, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 3: hipLaunchKernelGGL((k_face<1, uint32_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        default: hipLaunchKernelGGL((k_face<1, uint64_t>), dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+    const int64_t nx = g.n[g.rank - 1];
+    int64_t blocks = (g.n[0] * g.n[1] * g.n[2] / nx) * ((nx + kGlobalThreads - 1) / kGlobalThreads);
+    blocks = blocks < 1 ? 1 : blocks > 16384 ? 16384 : blocks;
+    switch (g.rank) {
+        case 3: hipLaunchKernelGGL(k_face<3>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 2: hipLaunchKernelGGL(k_face<2>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        default: hipLaunchKernelGGL(k_face<1>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
