@@ -200,3 +200,52 @@ def wide_field(shape, seed):
     flat[7::2111] = np.float32(3e-42)
     flat[5::3001] = rng.standard_normal(flat[5::3001].size).astype(np.float32) * np.float32(1e30)
     return x
+
+
+# ------------------------------------------------ seeded sweeps of shapes and values
+BOX = {1: (32768,), 2: (32, 1024), 3: (16, 32, 64)}
+MAX_VALUES = 400_000
+
+
+def draw_shape(rng, rank):
+    while True:
+        shape = []
+        for b in BOX[rank]:
+            k = int(rng.integers(0, 4))
+            base = b * int(rng.integers(1, 3)) if rank > 1 else b * int(rng.integers(1, 4))
+            ext = {0: base, 1: base + 1, 2: max(1, base - 1), 3: int(rng.integers(1, 2 * b + 1))}[k]
+            shape.append(ext)
+        shape = tuple(shape)
+        if np.prod(shape) <= MAX_VALUES:
+            return shape
+
+
+def draw_field(rng, shape, seed):
+    kind = ["sine", "lognormal", "noise", "zeros_block", "signed_zero", "denormal", "patches"][int(rng.integers(0, 7))]
+    if kind == "sine":
+        x = sine_field(shape, seed=seed)
+    elif kind == "lognormal":
+        x = np.exp(rng.standard_normal(shape) * 1.5).astype(np.float32)
+    elif kind == "noise":
+        x = rng.standard_normal(shape).astype(np.float32)
+    elif kind == "zeros_block":
+        x = sine_field(shape, seed=seed)
+        sl = tuple(slice(0, max(1, n // 2)) for n in shape)
+        x[sl] = 0.0
+    elif kind == "signed_zero":
+        x = sine_field(shape, seed=seed)
+        x[x < 0] = np.float32(-0.0)
+    elif kind == "denormal":  # every 7th value a denormal, the range stays normal
+        x = sine_field(shape, seed=seed)
+        flat = x.reshape(-1)
+        flat[::7] = (flat[::7] * np.float32(1e-39)).astype(np.float32)
+    else:
+        x = np.repeat(rng.standard_normal(max(1, x_len(shape) // 97 + 1)).astype(np.float32), 97)[:x_len(shape)]
+        x = x.reshape(shape)
+    return kind, np.ascontiguousarray(x, dtype=np.float32)
+
+
+def x_len(shape):
+    return int(np.prod(shape))
+
+
