@@ -256,7 +256,7 @@ def decompress(s, shape, out=None, err=None, stream=None, dtype=None, global_lor
         if work is None:  # freed when this returns: keep it until the launch's stream has passed it
             work = torch.empty(max(nwork, 16), dtype=torch.uint8, device=s.device)
             work.record_stream(stream if stream is not None else torch.cuda.current_stream())
-        elif work.numel() < nwork or not work.is_cuda:
+        elif work.numel() * work.element_size() < nwork or not work.is_cuda or not work.is_contiguous():
             raise ValueError("work must be a CUDA tensor of at least %d bytes" % nwork)
         rc = lib().fz_decompress_global(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                         ctypes.byref(dims), errp, ctypes.c_void_p(work.data_ptr()),
