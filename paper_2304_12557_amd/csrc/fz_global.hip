@@ -47,6 +47,18 @@ __device__ __forceinline__ int32_t quant_one(float v, const Quant& z, uint32_t& 
     return (int32_t)__builtin_rintf(p);
 }
 
+// launch shape of the row kernels: runs of 256 cells along the contiguous
+// axis in x, rows (all other coordinates) in y, both grid-strided
+inline dim3 row_grid(const Geom& g)
+{
+    const int64_t nx = g.n[g.rank - 1], nrows = g.n[0] * g.n[1] * g.n[2] / nx;
+    int64_t bx = (nx + kGlobalThreads - 1) / kGlobalThreads, by = nrows;
+    bx = bx > (1 << 16) ? (1 << 16) : bx;
+    by = by > 65535 ? 65535 : by;
+    while (bx * by > (1 << 18) && by > 1) by = (by + 1) / 2;  // a few hundred thousand blocks at most
+    return dim3((unsigned)bx, (unsigned)by);
+}
+
 // p of one cell from the quantized values q(c) of the cell and of its face
 // neighbours: a block takes 256 consecutive cells of one row (every
 // coordinate but the contiguous one fixed), so the row's coordinates, the
@@ -63,21 +75,21 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
     const Quant z = quant_of(out);
     int32_t* p = reinterpret_cast<int32_t*>(out + g.q_off);
     const int64_t nx = g.n[RANK - 1];
-    const int64_t nxb = (nx + kGlobalThreads - 1) / kGlobalThreads;
     const int64_t nrows = g.n[0] * g.n[1] * g.n[2] / nx;
-    const int shx = __builtin_ctz((unsigned)g.box[RANK - 1]);  // chunk boxes are powers of two
+    // chunk boxes are powers of two: the planes before a chunk come from shifts
+    const int shx = __builtin_ctz((unsigned)g.box[RANK - 1]);
+    const int sh0 = __builtin_ctz((unsigned)g.box[0]), sh1 = __builtin_ctz((unsigned)g.box[1]);
     uint32_t err = 0, dummy = 0;
     auto qv = [&](int64_t idx, bool own) -> uint32_t { return (uint32_t)quant_one(x[idx], z, own ? err : dummy); };
-    for (int64_t blk = blockIdx.x; blk < nrows * nxb; blk += gridDim.x) {
-        const int64_t row = blk / nxb;  // uniform
-        const int64_t c = (blk - row * nxb) * kGlobalThreads + threadIdx.x;
-        if (c >= nx) continue;
+    // a 2-D grid: rows along y, runs of 256 cells along x (no division per run)
+    for (int64_t row = blockIdx.y; row < nrows; row += gridDim.y)
+    for (int64_t c = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; c < nx; c += (int64_t)gridDim.x * kGlobalThreads) {
         const int64_t X = ((c >> shx) << shx) - 1;  // the column before the chunk (-1: outside the field)
         uint32_t acc;
         if constexpr (RANK == 1) {
             acc = qv(c, true) - (X >= 0 ? qv(X, false) : 0u);
         } else if constexpr (RANK == 2) {
-            const int64_t Y = (row / g.box[0]) * g.box[0] - 1;
+            const int64_t Y = ((row >> sh0) << sh0) - 1;
             const int64_t r0 = row * nx, rY = Y * nx;
             acc = qv(r0 + c, true);
             if (X >= 0) acc -= qv(r0 + X, false);
@@ -87,7 +99,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
             }
         } else {
             const int64_t c0 = row / g.n[1], c1 = row - c0 * g.n[1];
-            const int64_t Z = (c0 / g.box[0]) * g.box[0] - 1, Y = (c1 / g.box[1]) * g.box[1] - 1;
+            const int64_t Z = ((c0 >> sh0) << sh0) - 1, Y = ((c1 >> sh1) << sh1) - 1;
             const int64_t r00 = row * nx, rZ0 = (Z * g.n[1] + c1) * nx, r0Y = (c0 * g.n[1] + Y) * nx,
                           rZY = (Z * g.n[1] + Y) * nx;
             acc = qv(r00 + c, true);
@@ -122,13 +134,11 @@ __global__ __launch_bounds__(kGlobalThreads) void k_face(const float* __restrict
 
 hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
 {
-    const int64_t nx = g.n[g.rank - 1];
-    int64_t blocks = (g.n[0] * g.n[1] * g.n[2] / nx) * ((nx + kGlobalThreads - 1) / kGlobalThreads);
-    blocks = blocks < 1 ? 1 : blocks > 16384 ? 16384 : blocks;
+    const dim3 grid = row_grid(g);
     switch (g.rank) {
-        case 3: hipLaunchKernelGGL(k_face<3>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        case 2: hipLaunchKernelGGL(k_face<2>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
-        default: hipLaunchKernelGGL(k_face<1>, dim3((unsigned)blocks), dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 3: hipLaunchKernelGGL(k_face<3>, grid, dim3(kGlobalThreads), 0, st, x, out, g); break;
+        case 2: hipLaunchKernelGGL(k_face<2>, grid, dim3(kGlobalThreads), 0, st, x, out, g); break;
+        default: hipLaunchKernelGGL(k_face<1>, grid, dim3(kGlobalThreads), 0, st, x, out, g); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -232,12 +242,9 @@ __global__ __launch_bounds__(kGlobalThreads) void k_seg_final(uint32_t* __restri
     const bool pw = s[kOffEbMode] == 2;
     const uint32_t step = pw ? (uint32_t)ebx2 : 0u;
     const int64_t nx = k.n[RANK - 1];
-    const int64_t nxb = (nx + kGlobalThreads - 1) / kGlobalThreads;
     const int64_t nrows = k.n[0] * k.n[1] * k.n[2] / nx;
-    for (int64_t blk = blockIdx.x; blk < nrows * nxb; blk += gridDim.x) {
-        const int64_t row = blk / nxb;  // uniform
-        const int64_t x = (blk - row * nxb) * kGlobalThreads + threadIdx.x;
-        if (x >= nx) continue;
+    for (int64_t row = blockIdx.y; row < nrows; row += gridDim.y)
+    for (int64_t x = (int64_t)blockIdx.x * kGlobalThreads + threadIdx.x; x < nx; x += (int64_t)gridDim.x * kGlobalThreads) {
         uint32_t c;
         if constexpr (RANK == 3) {
             const int64_t c0 = row / k.n[1], c1 = row - c0 * k.n[1];
@@ -306,13 +313,11 @@ hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, u
         hipLaunchKernelGGL(k_seg_carry, dim3((unsigned)bc), dim3(kGlobalThreads), 0, st, f, w, k, ax);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const int64_t nx = g.n[g.rank - 1];
-    int64_t ba = (g.n[0] * g.n[1] * g.n[2] / nx) * ((nx + kGlobalThreads - 1) / kGlobalThreads);
-    ba = ba < 1 ? 1 : ba > 16384 ? 16384 : ba;
+    const dim3 grid = row_grid(g);
     switch (g.rank) {
-        case 3: hipLaunchKernelGGL(k_seg_final<3>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
-        case 2: hipLaunchKernelGGL(k_seg_final<2>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
-        default: hipLaunchKernelGGL(k_seg_final<1>, dim3((unsigned)ba), dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+        case 3: hipLaunchKernelGGL(k_seg_final<3>, grid, dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+        case 2: hipLaunchKernelGGL(k_seg_final<2>, grid, dim3(kGlobalThreads), 0, st, f, w, k, s); break;
+        default: hipLaunchKernelGGL(k_seg_final<1>, grid, dim3(kGlobalThreads), 0, st, f, w, k, s); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipSuccess;
