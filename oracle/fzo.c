@@ -63,8 +63,10 @@
 #define FZO_CHUNK_CODES (FZO_STEPS * FZO_STEP_CODES)
 #define FZO_PLANES 16
 #define FZO_FLAG_BYTES_PER_CHUNK (FZO_LAYERS * FZO_PLANES * 8)
-#define FZO_OUTLIER_CAP 1024       /* per chunk (= 4 layers x 256) */
-#define FZO_LAYER_OUTLIER_CAP 256  /* per layer: 1/32 of its 8192 codes */
+/* escapes a chunk may store: 1/32 of its 32768 codes.  A format rule: the
+ * worst-case payload of a chunk (every brick nonzero plus this many pairs)
+ * sizes the stream bound; where they fall inside the chunk is free.       */
+#define FZO_OUTLIER_CAP 1024
 #define FZO_ESCAPE 0x8000u
 
 typedef struct {
@@ -544,14 +546,9 @@ static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const 
 #pragma omp parallel for schedule(dynamic, 1) if (threads != 1)
 #endif
         for (int64_t c = 0; c < g.n_chunks; c++) encode_chunk(&g, q, c, &co[c]);
-        /* at most 256 escapes per layer (8192 codes) */
-        for (int64_t c = 0; c < g.n_chunks; c++) {
-            int64_t per_layer[FZO_LAYERS] = {0, 0, 0, 0};
+        /* at most FZO_OUTLIER_CAP escapes per chunk */
+        for (int64_t c = 0; c < g.n_chunks; c++)
             if (co[c].nout > FZO_OUTLIER_CAP) status |= FZO_ERR_OUTLIER_CAP;
-            for (int64_t i = 0; i < co[c].nout && i < FZO_OUTLIER_CAP; i++) per_layer[co[c].oidx[i] / (4 * FZO_STEP_CODES)]++;
-            for (int k = 0; k < FZO_LAYERS; k++)
-                if (per_layer[k] > FZO_LAYER_OUTLIER_CAP) status |= FZO_ERR_OUTLIER_CAP;
-        }
     }
     (void)threads;
 

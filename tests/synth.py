@@ -249,3 +249,23 @@ def x_len(shape):
     return int(np.prod(shape))
 
 
+
+
+def spike_field(shape, count, rows, seed, amp=100000.0):
+    """Zeros with `count` isolated spikes of height `amp` at even coordinates,
+    their slowest coordinate in the half-open range `rows`.  Under an absolute
+    bound of 0.5 (grid step 1) each spike's integer is `amp`, and its Lorenzo
+    deltas (2^rank of them, +-amp, all inside the spike's chunk because chunk
+    boxes have even extents) do not fit in 16 bits: `count * 2**rank` escaped
+    codes whose positions the test controls."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in shape)
+    cand = [np.arange(rows[0] + (rows[0] & 1), rows[1], 2)] + [np.arange(0, n, 2) for n in shape[1:]]
+    total = int(np.prod([len(c) for c in cand]))
+    if count > total:
+        raise ValueError("too many spikes for the rows")
+    pick = rng.choice(total, size=count, replace=False)
+    idx = np.unravel_index(pick, [len(c) for c in cand])
+    f = np.zeros(shape, dtype=np.float32)
+    f[tuple(c[i] for c, i in zip(cand, idx))] = np.float32(amp)
+    return f

@@ -54,8 +54,16 @@ def test_prequant_denormals_are_not_flushed():
     x = np.array([np.float32(2.0 ** -126) * np.float32(0.75), np.float32(2.0 ** -149)], np.float32)
     q, st = O.prequant(x, np.float32(2.0 ** 127))
     assert st == 0 and q.tolist() == [2, 0]
-    q, st = O.prequant(np.array([np.float32(2.0 ** -149)], np.float32), np.float32(2.0 ** 127) * np.float32(4.0))
-    assert q.tolist() == [0]  # 2^-149 * 2^129 = 2^-20
+    # subnormal inputs whose products with a finite inv = 2^127 are exactly
+    # 0.5, 1.5, -1.5, 1.25 and 1.75 (half-even: 0, 2, -2; nearest: 1, 2),
+    # and 2^-149 * 2^127 = 2^-22 -> 0
+    inv = np.float32(2.0 ** 127)
+    assert np.isfinite(inv)
+    x = np.array([2.0 ** -128, 3 * 2.0 ** -128, -3 * 2.0 ** -128, 5 * 2.0 ** -129, 7 * 2.0 ** -129, 2.0 ** -149],
+                 np.float32)
+    assert np.all(np.abs(x) < np.float32(2.0 ** -126))  # all subnormal
+    q, st = O.prequant(x, inv)
+    assert st == 0 and q.tolist() == [0, 2, -2, 1, 2, 0]
 
 
 @pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
@@ -295,6 +303,53 @@ def test_escapes_and_outlier_cap():
     rng = np.random.default_rng(3)
     w = (rng.standard_normal((16, 32, 64)) * 1e6).astype(np.float32)
     assert O.compress(w, 0.5, O.EB_ABS)[1] == O.ERR_OUTLIER_CAP
+
+
+def _escapes_per_layer(r, c):
+    codes = r["codes"][c]
+    return [int(np.count_nonzero(codes[8192 * k:8192 * (k + 1)] == 0x8000)) for k in range(4)]
+
+
+@pytest.mark.parametrize("shape,count,rows,layer,expect", [
+    ((32768,), 150, (0, 8190), 0, 300),        # 1-D: 2 escapes per spike, all in layer 0
+    ((32768,), 128, (8192, 16382), 1, 256),    # exactly 256 in one layer
+    ((32768,), 129, (8192, 16382), 1, 258),    # just past 256 in one layer
+    ((32768,), 512, (16384, 24574), 2, 1024),  # the whole chunk's allowance in one layer
+    ((16, 32, 64), 40, (4, 7), 1, 320),        # 3-D: 8 escapes per spike, planes 4-7
+    ((32, 1024), 100, (8, 15), 1, 400),        # 2-D: 4 escapes per spike, rows 8-15
+])
+def test_escapes_concentrated_in_one_layer(shape, count, rows, layer, expect):
+    """A chunk may store up to 1024 escaped codes wherever they fall (the
+    format caps the chunk, not its layers): a stream whose escapes crowd
+    into one layer is valid, reads back to rint(x * inv), and decompresses
+    to x (spikes of 100000 on a grid of step 1 are exact)."""
+    x = synth.spike_field(shape, count, rows, seed=17)
+    s, st = O.compress(x, 0.5, O.EB_ABS)
+    assert st == 0
+    h = stream_np.header(s)
+    assert h["n_out"] == expect
+    r = stream_np.read(s, shape)
+    per = _escapes_per_layer(r, 0)
+    assert per[layer] == expect and sum(per) == expect
+    assert np.array_equal(r["q"], x.astype(np.int32))
+    y, err = O.decompress(s, shape)
+    assert err == 0 and np.array_equal(y, x)
+
+
+def test_escape_cap_is_per_chunk():
+    # 1025 escapes in one chunk: the cap; the same count split over two
+    # chunks (1024 + 1) is a valid stream
+    x = synth.spike_field((32768,), 512, (16384, 24574), seed=18)
+    x[30000:] = np.float32(100000.0)  # one more escape (a step) in layer 3
+    assert O.compress(x, 0.5, O.EB_ABS)[1] == O.ERR_OUTLIER_CAP
+    x2 = np.concatenate([synth.spike_field((32768,), 512, (16384, 24574), seed=18), np.zeros(32768, np.float32)])
+    x2[40000:] = np.float32(100000.0)
+    s, st = O.compress(x2, 0.5, O.EB_ABS)
+    assert st == 0
+    r = stream_np.read(s, x2.shape)
+    assert r["nout"] == [1024, 1]
+    y, err = O.decompress(s, x2.shape)
+    assert err == 0 and np.array_equal(y, x2)
 
 
 def test_decompress_rejects_bad_streams():
