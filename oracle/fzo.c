@@ -619,20 +619,47 @@ static int64_t emit_stream(const geom_t *g0, int32_t *q, uint32_t status, const 
  * inverse Lorenzo = inclusive prefix sums along x, then y, then z inside the
  * chunk box (mod 2^32), D6 x' = fp32((float)q * ebx2), or in PWREL mode the
  * inverse transform of q * S (O2b).                                       */
-static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims);
+static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims,
+                          int threads);
 
 int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims)
 {
-    return decompress_any(s, size, x, NULL, rank, dims);
+    return decompress_any(s, size, x, NULL, rank, dims, 1);
+}
+
+/* the same with the chunks spread over `threads` OpenMP threads (0: the
+ * runtime's default); the result does not depend on the thread count */
+int fzo_decompress_threads(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims, int threads)
+{
+    return decompress_any(s, size, x, NULL, rank, dims, threads);
 }
 
 /* fp64 streams (dtype 1): x' = (double) q * ebx2, ebx2 the double at byte 104 */
 int fzo_decompress_f64(const uint8_t *s, int64_t size, double *x, int rank, const int64_t *dims)
 {
-    return decompress_any(s, size, NULL, x, rank, dims);
+    return decompress_any(s, size, NULL, x, rank, dims, 1);
 }
 
-static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims)
+/* D2-D6 for chunk c: rebuild its codes from the flags and bricks, decode,
+ * undo the predictor and write its values (or, field-global, its deltas).
+ * Returns 0 or FZO_DERR_STREAM; *units gets the payload units it read.   */
+typedef struct {
+    const geom_t *g;
+    const uint8_t *s, *flags, *payload;
+    int64_t payload_units;
+    int mode;
+    uint32_t step;
+    float ebx2;
+    double ebx2_64;
+    float *x;
+    double *x64;
+    uint32_t *field;
+} dctx_t;
+
+static int decompress_chunk(const dctx_t *D, int64_t c, uint16_t *codes, int32_t *delta, uint32_t *box, int64_t *units);
+
+static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64, int rank, const int64_t *dims,
+                          int threads)
 {
     geom_t g;
     if (make_geom(rank, dims, &g)) return FZO_DERR_ARG;
@@ -668,93 +695,30 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
     const uint8_t *payload = s + H;
     int64_t payload_units = (total - H) / 16;
 
-    uint16_t *codes = (uint16_t *)malloc(FZO_CHUNK_CODES * sizeof(uint16_t));
-    int32_t *delta = (int32_t *)malloc(FZO_CHUNK_CODES * sizeof(int32_t));
-    uint32_t *box = (uint32_t *)malloc(FZO_CHUNK_CODES * sizeof(uint32_t));
     /* field-global predictor: every chunk's deltas go to one field, summed
      * over the whole field once all chunks are read */
     int64_t N = g.n[0] * g.n[1] * g.n[2];
     uint32_t *field = g.global ? (uint32_t *)calloc((size_t)N, sizeof(uint32_t)) : NULL;
+    dctx_t D = {&g, s, flags, payload, payload_units, mode, step, ebx2, ebx2_64, x, x64, field};
     int err = 0;
     int64_t units_seen = 0;
-    for (int64_t c = 0; c < g.n_chunks && !err; c++) {
-        int64_t o[3], ext[3];
-        chunk_origin(&g, c, o, ext);
-        int L = layers_of(g.rank, ext[0]);
-        uint32_t off = get32(s + FZO_HEADER_BYTES + 8 * c);
-        uint32_t nout = get32(s + FZO_HEADER_BYTES + 8 * c + 4);
-        if (nout > FZO_OUTLIER_CAP) { err = FZO_DERR_STREAM; break; }
-        /* D2/D3: rebuild codes */
-        memset(codes, 0, FZO_CHUNK_CODES * sizeof(uint16_t));
-        int64_t cur = off, nnz = 0;
-        for (int k = 0; k < FZO_LAYERS && !err; k++)
-            for (int b = 0; b < FZO_PLANES && !err; b++) {
-                uint64_t f = get64(flags + FZO_FLAG_BYTES_PER_CHUNK * c + 8 * (k * FZO_PLANES + b));
-                if (k >= L && f) { err = FZO_DERR_STREAM; break; }
-                for (int p = 0; p < FZO_PATCHES && !err; p++) {
-                    if (!((f >> p) & 1u)) continue;
-                    if (cur >= payload_units) { err = FZO_DERR_STREAM; break; }
-                    for (int t = 0; t < 4; t++) {
-                        uint32_t w = get32(payload + 16 * cur + 4 * t);
-                        for (int m = 0; m < 32; m++)
-                            if ((w >> m) & 1u)
-                                codes[(4 * k + t) * FZO_STEP_CODES + p * FZO_PATCH_CODES + m] |= (uint16_t)(1u << b);
-                    }
-                    cur++;
-                    nnz++;
-                }
-            }
-        if (err) break;
-        /* D4: codes -> delta; escapes take the pairs in order */
-        const uint8_t *op = payload + 16 * cur;
-        if (cur + ((int64_t)nout + 1) / 2 > payload_units) { err = FZO_DERR_STREAM; break; }
-        int64_t next_out = 0;
-        for (int64_t n = 0; n < (int64_t)L * 4 * FZO_STEP_CODES; n++) {
-            if (codes[n] == FZO_ESCAPE) {
-                if (next_out >= nout || get32(op + 8 * next_out) != (uint32_t)n) { err = FZO_DERR_STREAM; break; }
-                delta[n] = (int32_t)get32(op + 8 * next_out + 4);
-                next_out++;
-            } else {
-                delta[n] = fzo_delta_of(codes[n]);
-            }
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel if (threads != 1) reduction(| : err) reduction(+ : units_seen)
+#endif
+    {
+        uint16_t *codes = (uint16_t *)malloc(FZO_CHUNK_CODES * sizeof(uint16_t));
+        int32_t *delta = (int32_t *)malloc(FZO_CHUNK_CODES * sizeof(int32_t));
+        uint32_t *box = (uint32_t *)malloc(FZO_CHUNK_CODES * sizeof(uint32_t));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t c = 0; c < g.n_chunks; c++) {
+            int64_t u = 0;
+            err |= decompress_chunk(&D, c, codes, delta, box, &u);
+            units_seen += u;
         }
-        if (err) break;
-        if (next_out != nout) { err = FZO_DERR_STREAM; break; }
-        units_seen += nnz + ((int64_t)nout + 1) / 2;
-        /* scatter delta into the (clipped) box, row-major slowest-first */
-        int64_t e0 = ext[0], e1 = ext[1], e2 = ext[2];
-        for (int64_t n = 0; n < (int64_t)L * 4 * FZO_STEP_CODES; n++) {
-            int64_t r[3];
-            code_to_cell(g.rank, (int)(n / FZO_STEP_CODES), (int)((n / FZO_PATCH_CODES) % FZO_PATCHES),
-                         (int)(n % FZO_PATCH_CODES), r);
-            if (r[0] < e0 && r[1] < e1 && r[2] < e2) box[(r[0] * e1 + r[1]) * e2 + r[2]] = (uint32_t)delta[n];
-        }
-        if (g.global) {
-            for (int64_t a = 0; a < e0; a++)
-                for (int64_t b = 0; b < e1; b++)
-                    for (int64_t cc = 0; cc < e2; cc++)
-                        field[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = box[(a * e1 + b) * e2 + cc];
-            continue;
-        }
-        /* D5: inclusive prefix sums along the fastest dim, then the middle,
-         * then the slowest (only the dims the rank has) */
-        for (int64_t a = 0; a < e0; a++)
-            for (int64_t b = 0; b < e1; b++)
-                for (int64_t cc = 1; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[(a * e1 + b) * e2 + cc - 1];
-        for (int64_t a = 0; a < e0; a++)
-            for (int64_t b = 1; b < e1; b++)
-                for (int64_t cc = 0; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[(a * e1 + b - 1) * e2 + cc];
-        for (int64_t a = 1; a < e0; a++)
-            for (int64_t b = 0; b < e1; b++)
-                for (int64_t cc = 0; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[((a - 1) * e1 + b) * e2 + cc];
-        /* D6: dequantize */
-        for (int64_t a = 0; a < e0; a++)
-            for (int64_t b = 0; b < e1; b++)
-                for (int64_t cc = 0; cc < e2; cc++)
-                    if (x64) x64[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = (double)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2_64;
-                    else x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] =
-                        mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)box[(a * e1 + b) * e2 + cc], step)
-                                             : (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
+        free(codes); free(delta); free(box);
     }
     if (!err && g.global) {
         /* D5g: inclusive prefix sums of the deltas along the fastest dim,
@@ -776,9 +740,100 @@ static int decompress_any(const uint8_t *s, int64_t size, float *x, double *x64,
         }
     }
     free(field);
-    free(codes); free(delta); free(box);
     if (!err && H + 16 * units_seen != total) err = FZO_DERR_STREAM;
     return err;
+}
+
+static int decompress_chunk(const dctx_t *D, int64_t c, uint16_t *codes, int32_t *delta, uint32_t *box, int64_t *units)
+{
+    const geom_t *gp = D->g;
+    const geom_t g = *gp;
+    const uint8_t *s = D->s, *flags = D->flags, *payload = D->payload;
+    const int64_t payload_units = D->payload_units;
+    const int mode = D->mode;
+    const uint32_t step = D->step;
+    const float ebx2 = D->ebx2;
+    const double ebx2_64 = D->ebx2_64;
+    float *x = D->x;
+    double *x64 = D->x64;
+    uint32_t *field = D->field;
+    *units = 0;
+        int64_t o[3], ext[3];
+        chunk_origin(&g, c, o, ext);
+        int L = layers_of(g.rank, ext[0]);
+        uint32_t off = get32(s + FZO_HEADER_BYTES + 8 * c);
+        uint32_t nout = get32(s + FZO_HEADER_BYTES + 8 * c + 4);
+        if (nout > FZO_OUTLIER_CAP) return FZO_DERR_STREAM;
+        /* D2/D3: rebuild codes */
+        memset(codes, 0, FZO_CHUNK_CODES * sizeof(uint16_t));
+        int64_t cur = off, nnz = 0;
+        for (int k = 0; k < FZO_LAYERS; k++)
+            for (int b = 0; b < FZO_PLANES; b++) {
+                uint64_t f = get64(flags + FZO_FLAG_BYTES_PER_CHUNK * c + 8 * (k * FZO_PLANES + b));
+                if (k >= L && f) return FZO_DERR_STREAM;
+                for (int p = 0; p < FZO_PATCHES; p++) {
+                    if (!((f >> p) & 1u)) continue;
+                    if (cur >= payload_units) return FZO_DERR_STREAM;
+                    for (int t = 0; t < 4; t++) {
+                        uint32_t w = get32(payload + 16 * cur + 4 * t);
+                        for (int m = 0; m < 32; m++)
+                            if ((w >> m) & 1u)
+                                codes[(4 * k + t) * FZO_STEP_CODES + p * FZO_PATCH_CODES + m] |= (uint16_t)(1u << b);
+                    }
+                    cur++;
+                    nnz++;
+                }
+            }
+        /* D4: codes -> delta; escapes take the pairs in order */
+        const uint8_t *op = payload + 16 * cur;
+        if (cur + ((int64_t)nout + 1) / 2 > payload_units) return FZO_DERR_STREAM;
+        int64_t next_out = 0;
+        for (int64_t n = 0; n < (int64_t)L * 4 * FZO_STEP_CODES; n++) {
+            if (codes[n] == FZO_ESCAPE) {
+                if (next_out >= nout || get32(op + 8 * next_out) != (uint32_t)n) return FZO_DERR_STREAM;
+                delta[n] = (int32_t)get32(op + 8 * next_out + 4);
+                next_out++;
+            } else {
+                delta[n] = fzo_delta_of(codes[n]);
+            }
+        }
+        if (next_out != nout) return FZO_DERR_STREAM;
+        *units = nnz + ((int64_t)nout + 1) / 2;
+        /* scatter delta into the (clipped) box, row-major slowest-first */
+        int64_t e0 = ext[0], e1 = ext[1], e2 = ext[2];
+        for (int64_t n = 0; n < (int64_t)L * 4 * FZO_STEP_CODES; n++) {
+            int64_t r[3];
+            code_to_cell(g.rank, (int)(n / FZO_STEP_CODES), (int)((n / FZO_PATCH_CODES) % FZO_PATCHES),
+                         (int)(n % FZO_PATCH_CODES), r);
+            if (r[0] < e0 && r[1] < e1 && r[2] < e2) box[(r[0] * e1 + r[1]) * e2 + r[2]] = (uint32_t)delta[n];
+        }
+        if (g.global) {
+            for (int64_t a = 0; a < e0; a++)
+                for (int64_t b = 0; b < e1; b++)
+                    for (int64_t cc = 0; cc < e2; cc++)
+                        field[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = box[(a * e1 + b) * e2 + cc];
+            return 0;
+        }
+        /* D5: inclusive prefix sums along the fastest dim, then the middle,
+         * then the slowest (only the dims the rank has) */
+        for (int64_t a = 0; a < e0; a++)
+            for (int64_t b = 0; b < e1; b++)
+                for (int64_t cc = 1; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[(a * e1 + b) * e2 + cc - 1];
+        for (int64_t a = 0; a < e0; a++)
+            for (int64_t b = 1; b < e1; b++)
+                for (int64_t cc = 0; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[(a * e1 + b - 1) * e2 + cc];
+        for (int64_t a = 1; a < e0; a++)
+            for (int64_t b = 0; b < e1; b++)
+                for (int64_t cc = 0; cc < e2; cc++) box[(a * e1 + b) * e2 + cc] += box[((a - 1) * e1 + b) * e2 + cc];
+        /* D6: dequantize */
+        for (int64_t a = 0; a < e0; a++)
+            for (int64_t b = 0; b < e1; b++)
+                for (int64_t cc = 0; cc < e2; cc++)
+                    if (x64) x64[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] = (double)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2_64;
+                    else x[lin(&g, o[0] + a, o[1] + b, o[2] + cc)] =
+                        mode == FZO_EB_PWREL ? fzo_dequant_pw((int32_t)box[(a * e1 + b) * e2 + cc], step)
+                                             : (float)(int32_t)box[(a * e1 + b) * e2 + cc] * ebx2;
+    return 0;
 }
 
 /* ------------------------------------------------------ stage dumps (tests)

@@ -36,6 +36,8 @@ int64_t fzo_chunk_codes(const float *x, int rank, const int64_t *dims, float inv
 int64_t fzo_compress(const float *x, int rank, const int64_t *dims, double eb, int eb_mode, uint8_t *out,
                      int64_t cap, uint32_t *status_out, int threads);
 int fzo_decompress(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims);
+/* the same with the chunks spread over `threads` OpenMP threads (0: default) */
+int fzo_decompress_threads(const uint8_t *s, int64_t size, float *x, int rank, const int64_t *dims, int threads);
 /* global = 1: the field-global Lorenzo predictor (header byte 15); fzo_decompress reads either */
 int64_t fzo_compress_pred(const float *x, int rank, const int64_t *dims, double eb, int eb_mode, int global,
                           uint8_t *out, int64_t cap, uint32_t *status_out, int threads);

@@ -62,6 +62,8 @@ def lib():
         L.fzo_compress.restype = ctypes.c_int64
         L.fzo_decompress.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int, _i64p]
         L.fzo_decompress.restype = ctypes.c_int
+        L.fzo_decompress_threads.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int, _i64p, ctypes.c_int]
+        L.fzo_decompress_threads.restype = ctypes.c_int
         L.fzo_compress_pred.argtypes = [vp, ctypes.c_int, _i64p, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.c_int64, vp, ctypes.c_int]
         L.fzo_compress_pred.restype = ctypes.c_int64
@@ -169,12 +171,16 @@ def compress(x, eb, mode=EB_REL, threads=1, global_lorenzo=False):
     return out[:n].copy(), int(st[0])
 
 
-def decompress(stream, shape):
-    """Returns (float32 array, error code)."""
+def decompress(stream, shape, threads=1):
+    """Returns (float32 array, error code).  threads: OpenMP threads over
+    the chunks (1: the sequential reference; the result is the same)."""
     s = np.ascontiguousarray(stream, dtype=np.uint8)
     r, d = _dims(shape)
     out = np.zeros(shape, dtype=np.float32)
-    err = lib().fzo_decompress(_ptr(s), s.size, _ptr(out), r, d)
+    if threads == 1:
+        err = lib().fzo_decompress(_ptr(s), s.size, _ptr(out), r, d)
+    else:
+        err = lib().fzo_decompress_threads(_ptr(s), s.size, _ptr(out), r, d, int(threads))
     return out, err
 
 

@@ -63,6 +63,10 @@ static void roundtrip(int rank, const int64_t *d, double eb, int mode, int globa
     if (len > 0 && st == 0) {
         int err = fzo_decompress(s, len, y, rank, d);
         CHECK(err == 0, "decompress rank %d mode %d -> %d", rank, mode, err);
+        float *y4 = malloc((size_t)n * sizeof(float));
+        CHECK(fzo_decompress_threads(s, len, y4, rank, d, 4) == 0 && memcmp(y, y4, (size_t)n * sizeof(float)) == 0,
+              "threaded decompress rank %d mode %d", rank, mode);
+        free(y4);
         float ebx2, inv;
         memcpy(&ebx2, s + 48, 4);
         memcpy(&inv, s + 52, 4);
@@ -84,6 +88,7 @@ static void roundtrip(int rank, const int64_t *d, double eb, int mode, int globa
             int flips = 1 + (int)(rnd() % 4);
             for (int f = 0; f < flips; f++) t[rnd() % (uint32_t)len] ^= (uint8_t)(1u << (rnd() % 8));
             (void)fzo_decompress(t, len, y, rank, d);
+            (void)fzo_decompress_threads(t, len, y, rank, d, 3);
         }
         free(t);
     }

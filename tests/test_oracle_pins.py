@@ -368,3 +368,17 @@ def test_openmp_equals_single_thread():
     a, _ = O.compress(x, 1e-4, O.EB_REL, threads=1)
     b, _ = O.compress(x, 1e-4, O.EB_REL, threads=8)
     assert np.array_equal(a, b)
+    # decompression over chunks in parallel: the same values, the same errors
+    ya, ea = O.decompress(a, x.shape)
+    yb, eb_ = O.decompress(a, x.shape, threads=8)
+    assert ea == eb_ == 0 and np.array_equal(ya.view(np.uint32), yb.view(np.uint32))
+    for shape, seed, glob in (((70, 2100), 6, False), ((100001,), 7, False), ((40, 70, 130), 8, True)):
+        xs = synth.sine_field(shape, seed=seed) + np.float32(300.0)  # escapes at chunk origins
+        s, st = O.compress(xs, 1e-3, O.EB_ABS, global_lorenzo=glob)
+        assert st == 0
+        y1, e1 = O.decompress(s, shape)
+        y8, e8 = O.decompress(s, shape, threads=8)
+        assert e1 == e8 == 0 and np.array_equal(y1.view(np.uint32), y8.view(np.uint32))
+    bad = a.copy()
+    bad[128 + 8 * 3] ^= 1  # a chunk offset off by one unit
+    assert O.decompress(bad, x.shape)[1] == O.decompress(bad, x.shape, threads=8)[1] == 2
