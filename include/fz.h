@@ -24,7 +24,13 @@
  *     independent as long as their buffers do not overlap;
  *   - argument errors return a nonzero fz_status immediately and enqueue
  *     nothing; data-dependent errors are reported on the device (see each
- *     call).
+ *     call);
+ *   - alignment: a buffer the library writes or reads as a whole (d_out of
+ *     the compression calls, d_stream, d_work) must start on a 256-byte
+ *     boundary, d_err on a 4-byte boundary and d_res on an 8-byte boundary
+ *     (the kernels use atomics and 8- and 16-byte accesses at fixed offsets
+ *     in them); inputs and outputs of field values may have any 4-byte (fp32)
+ *     or 8-byte (fp64) alignment.  A misaligned pointer is FZ_ERR_ARG.
  */
 #ifndef FZ_H
 #define FZ_H
@@ -43,7 +49,7 @@ typedef enum {
     FZ_ERR_NONFINITE = 3,    /* input holds NaN or Inf */
     FZ_ERR_EB_RANGE = 4,     /* error bound unusable: 2*eb not a normal fp32, or |x/(2eb)| >= 2^31;
                               * FZ_EB_PWREL: the step (see fz_compress) outside [2, 2^24) */
-    FZ_ERR_OUTLIER_CAP = 5,  /* more than 256 escaped codes in one layer of 8192 codes */
+    FZ_ERR_OUTLIER_CAP = 5,  /* more than 1024 escaped codes in one chunk of 32768 codes */
     FZ_ERR_STREAM = 6,       /* malformed or inconsistent stream */
     FZ_ERR_VERSION = 7,      /* unknown stream version */
     FZ_ERR_STATUS = 8        /* stream carries a nonzero compression status */
@@ -133,16 +139,43 @@ size_t fz_header_bytes(const fz_dims *dims);
  * either is set, the escape-cap bit is not.  Returns FZ_OK once the work is enqueued. */
 int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
 
+/* Timing points of one compression, for callers that measure kernel time
+ * (Sec. 4.4 reports kernel time over the input bytes).  Each member is an
+ * optional hipEvent_t (as void*, NULL to skip) that fz_compress_timed
+ * records on `stream`: range_begin before the value-range pass (REL mode;
+ * after the header is initialised), main_begin right before the main
+ * compression kernel, main_end right after it, done after the last kernel
+ * (the device-wide prefix sum and the placement of the chunks).  Events
+ * bracket launches, so an interval includes the launch gaps inside it. */
+typedef struct {
+    void *range_begin, *main_begin, *main_end, *done;
+} fz_timing;
+
+/* fz_compress_timed -- fz_compress, recording the events of *timing (which
+ * may be NULL: then exactly fz_compress).  Same arguments, errors and
+ * result. */
+int fz_compress_timed(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream,
+                      const fz_timing *timing);
+
 /* fz_decompress -- the inverse pipeline (Sec. 4.4 describes it as symmetric
  * to compression).
- *   d_stream : device pointer to a stream made by fz_compress
- *   d_out    : N fp32 values (device, written)
- *   dims     : must equal the dims the stream was made with
- *   d_err    : optional device u32; receives 0 or an fz_status code
- *              (FZ_ERR_STREAM, FZ_ERR_VERSION, FZ_ERR_STATUS) if the stream
- *              is rejected on the device; d_out is then not written
+ *   d_stream     : device pointer to a stream made by fz_compress
+ *   stream_bytes : bytes readable at d_stream (at least the stream's size);
+ *                  no byte at or past it is ever read.  Below the header,
+ *                  table and flags of `dims` (fz_header_bytes): FZ_ERR_ARG
+ *   d_out        : N fp32 values (device, written)
+ *   dims         : must equal the dims the stream was made with
+ *   d_err        : optional device u32; receives 0 or an fz_status code
+ *                  (FZ_ERR_STREAM, FZ_ERR_VERSION, FZ_ERR_STATUS) if the
+ *                  stream is rejected on the device: bad magic, version,
+ *                  status or dims, a total size past stream_bytes, a chunk
+ *                  table whose offsets do not follow from the flags'
+ *                  popcounts and escape counts, or escape pairs that do not
+ *                  match the escape codes.  A chunk found bad is not
+ *                  written; a header found bad leaves d_out untouched.
  * Returns FZ_OK once the work is enqueued. */
-int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
+int fz_decompress(const void *d_stream, size_t stream_bytes, float *d_out, const fz_dims *dims, uint32_t *d_err,
+                  void *stream);
 
 /* ------------------------------------------------------------ fp64 input
  * The same pipeline on fp64 fields (FZ_EB_ABS and FZ_EB_REL): the bound's
@@ -161,12 +194,13 @@ int fz_decompress(const void *d_stream, float *d_out, const fz_dims *dims, uint3
  * normal double returns FZ_ERR_EB_RANGE at once.  Data-dependent errors and
  * the stream size as for fz_compress.
  * fz_decompress_f64: d_out receives N fp64 values x' = (double) q * 2eb_abs;
- * d_err as for fz_decompress (an fp32 stream is FZ_ERR_STREAM here, and an
+ * stream_bytes and d_err as for fz_decompress (an fp32 stream is FZ_ERR_STREAM here, and an
  * fp64 stream is FZ_ERR_STREAM for fz_decompress).
  * The batch and serving layers take fp32 fields only. */
 size_t fz_compress_bound_f64(const fz_dims *dims);
 int fz_compress_f64(const double *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
-int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, uint32_t *d_err, void *stream);
+int fz_decompress_f64(const void *d_stream, size_t stream_bytes, double *d_out, const fz_dims *dims, uint32_t *d_err,
+                      void *stream);
 
 /* ------------------------------------------- field-global Lorenzo predictor
  * The classic Lorenzo predictor over the whole field (Sec. 2.3) instead of
@@ -184,7 +218,7 @@ int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, 
  * (one u32 carry per chunk-box segment of every line along each axis: about
  * 0.44 N bytes for a 3-D field); 0 on invalid dims.
  * fz_decompress_global: as fz_decompress, plus d_work (that many bytes,
- * device, overwritten).  It writes d_out twice (the chunk kernel's local
+ * device, overwritten, 256-byte aligned).  It writes d_out twice (the chunk kernel's local
  * sums, then the values with every axis's carries), so a rejected stream
  * (*d_err set) leaves d_out unspecified.  fz_decompress and the batch layer
  * reject field-global streams (FZ_ERR_STREAM), and fz_decompress_global
@@ -192,12 +226,13 @@ int fz_decompress_f64(const void *d_stream, double *d_out, const fz_dims *dims, 
 size_t fz_compress_bound_global(const fz_dims *dims);
 int fz_compress_global(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream);
 size_t fz_decompress_global_work_bytes(const fz_dims *dims);
-int fz_decompress_global(const void *d_stream, float *d_out, const fz_dims *dims, uint32_t *d_err, void *d_work,
-                         void *stream);
+int fz_decompress_global(const void *d_stream, size_t stream_bytes, float *d_out, const fz_dims *dims,
+                         uint32_t *d_err, void *d_work, void *stream);
 
 /* ------------------------------------------------------------ batches
  * Many fields of uneven rank and size in a fixed, small number of launches
- * (one persistent compression launch over every chunk of every field).  The
+ * (one persistent compression launch per rank and row-alignment class, over
+ * every chunk of every field of that class; one decompression launch).  The
  * bytes each field gets are exactly those of fz_compress / fz_decompress on
  * that field alone.
  *
@@ -222,6 +257,7 @@ typedef struct {
     fz_dims dims;          /* the dims it was made with */
     float *d_out;          /* N fp32 values (device) */
     uint32_t *d_err;       /* optional device u32, as for fz_decompress */
+    uint64_t stream_bytes; /* bytes readable at d_stream, as for fz_decompress */
 } fz_decompress_job;
 
 typedef struct fz_batch fz_batch;
@@ -256,7 +292,9 @@ int fz_batch_destroy(fz_batch *b);
  * The caller owns the request buffers (device memory) and must keep them
  * until fz_server_wait returns for that request.  The server allocates its
  * streams, device table areas and pinned staging at creation, nothing per
- * request. */
+ * request.  Ordering: the server runs requests on streams of its own; work
+ * the caller enqueued before submitting (producing d_in, or still using the
+ * memory of d_out) is waited for only through ready_event. */
 #define FZ_REQ_COMPRESS 0
 #define FZ_REQ_DECOMPRESS 1
 
@@ -269,7 +307,12 @@ typedef struct {
     void *d_out;         /* compress: fz_compress_bound bytes; decompress: N fp32 */
     uint32_t *d_err;     /* decompress: optional error word, as for fz_decompress */
     uint64_t hbm_bytes;  /* device bytes charged against the budget while admitted;
-                            0: 4N + fz_compress_bound(dims) */
+                            0: 4N + fz_compress_bound(dims) (compress) or
+                            4N + stream_bytes (decompress) */
+    uint64_t stream_bytes; /* decompress: bytes readable at d_in (as for fz_decompress) */
+    void *ready_event;   /* optional hipEvent_t recorded by the caller after the work that
+                            produces d_in and last uses d_out: the request's kernels wait
+                            for it on the device; keep it alive until fz_server_wait */
 } fz_request;
 
 typedef struct {

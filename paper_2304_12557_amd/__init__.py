@@ -48,15 +48,20 @@ class FzCompressJob(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("d_out", ctypes.c_void_p)]
 
 
+class FzTiming(ctypes.Structure):
+    _fields_ = [("range_begin", ctypes.c_void_p), ("main_begin", ctypes.c_void_p), ("main_end", ctypes.c_void_p),
+                ("done", ctypes.c_void_p)]
+
+
 class FzDecompressJob(ctypes.Structure):
     _fields_ = [("d_stream", ctypes.c_void_p), ("dims", FzDims), ("d_out", ctypes.c_void_p),
-                ("d_err", ctypes.c_void_p)]
+                ("d_err", ctypes.c_void_p), ("stream_bytes", ctypes.c_uint64)]
 
 
 class FzRequest(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("eb_mode", ctypes.c_int32), ("eb", ctypes.c_double), ("dims", FzDims),
                 ("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("d_err", ctypes.c_void_p),
-                ("hbm_bytes", ctypes.c_uint64)]
+                ("hbm_bytes", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64), ("ready_event", ctypes.c_void_p)]
 
 
 class FzServerReport(ctypes.Structure):
@@ -94,13 +99,16 @@ def lib():
         L.fz_header_bytes.restype = ctypes.c_size_t
         L.fz_compress.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
         L.fz_compress.restype = ctypes.c_int
-        L.fz_decompress.argtypes = [vp, vp, dp, vp, vp]
+        L.fz_compress_timed.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp, ctypes.POINTER(FzTiming)]
+        L.fz_compress_timed.restype = ctypes.c_int
+        sz = ctypes.c_size_t
+        L.fz_decompress.argtypes = [vp, sz, vp, dp, vp, vp]
         L.fz_decompress.restype = ctypes.c_int
         L.fz_compress_bound_f64.argtypes = [dp]
         L.fz_compress_bound_f64.restype = ctypes.c_size_t
         L.fz_compress_f64.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
         L.fz_compress_f64.restype = ctypes.c_int
-        L.fz_decompress_f64.argtypes = [vp, vp, dp, vp, vp]
+        L.fz_decompress_f64.argtypes = [vp, sz, vp, dp, vp, vp]
         L.fz_decompress_f64.restype = ctypes.c_int
         L.fz_compress_bound_global.argtypes = [dp]
         L.fz_compress_bound_global.restype = ctypes.c_size_t
@@ -108,7 +116,7 @@ def lib():
         L.fz_compress_global.restype = ctypes.c_int
         L.fz_decompress_global_work_bytes.argtypes = [dp]
         L.fz_decompress_global_work_bytes.restype = ctypes.c_size_t
-        L.fz_decompress_global.argtypes = [vp, vp, dp, vp, vp, vp]
+        L.fz_decompress_global.argtypes = [vp, sz, vp, dp, vp, vp, vp]
         L.fz_decompress_global.restype = ctypes.c_int
         L.fz_stream_info.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(FzInfo)]
         L.fz_stream_info.restype = ctypes.c_int
@@ -153,7 +161,7 @@ def lib():
     return _LIB
 
 
-SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_decompress", "fz_stream_info", "fz_strerror",
+SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_compress_timed", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
@@ -187,6 +195,28 @@ def header_bytes(shape):
     return int(lib().fz_header_bytes(ctypes.byref(dims_of(shape))))
 
 
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _check_buffer(t, name, dtypes, align, numel=None):
+    """Raise ValueError unless t is a contiguous CUDA tensor of one of
+    `dtypes` whose data starts on an `align`-byte boundary (and, if given,
+    holds at least `numel` elements): what the C ABI requires of it."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s must be of dtype %s" % (name, " or ".join(str(d) for d in dtypes)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.data_ptr() % align:
+        raise ValueError("%s must start on a %d-byte boundary" % (name, align))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s must hold at least %d elements" % (name, numel))
+
+
 def _stream_ptr(stream):
     import torch
 
@@ -205,11 +235,14 @@ def _mode(mode):
     raise ValueError("mode must be 'rel', 'abs' or 'pwrel'")
 
 
-def compress(x, eb, mode="rel", out=None, stream=None, global_lorenzo=False):
+def compress(x, eb, mode="rel", out=None, stream=None, global_lorenzo=False, events=None):
     """Compress a float32 or float64 CUDA tensor; returns the uint8 output
     buffer (``compress_bound`` bytes; the stream occupies its first
     ``stream_size(buf)`` bytes).  ``global_lorenzo``: the field-global
-    predictor (float32 input).  Asynchronous on ``stream``."""
+    predictor (float32 input).  ``events``: a dict of torch.cuda.Event
+    objects under any of the keys range_begin, main_begin, main_end, done,
+    recorded between the launches (fz_compress_timed; float32 input with the
+    chunk-local predictor).  Asynchronous on ``stream``."""
     import torch
 
     if not (x.is_cuda and x.dtype in (torch.float32, torch.float64) and x.is_contiguous()):
@@ -221,8 +254,21 @@ def compress(x, eb, mode="rel", out=None, stream=None, global_lorenzo=False):
     bound = compress_bound(x.shape, f64=f64, global_lorenzo=global_lorenzo)
     if out is None:
         out = torch.empty(bound, dtype=torch.uint8, device=x.device)
-    elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
-        raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
+    else:
+        _check_buffer(out, "out", (torch.uint8,), 256, bound)
+    if events:
+        if f64 or global_lorenzo:
+            raise ValueError("events are recorded for float32 input with the chunk-local predictor")
+        t = FzTiming()
+        for k, ev in events.items():
+            if ev is not None:
+                ev.record(stream if stream is not None else torch.cuda.current_stream())  # creates the event
+                setattr(t, k, ev.cuda_event)
+        rc = lib().fz_compress_timed(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream), ctypes.byref(t))
+        if rc:
+            raise FzError(rc, "fz_compress_timed")
+        return out
     fn = lib().fz_compress_f64 if f64 else lib().fz_compress_global if global_lorenzo else lib().fz_compress
     rc = fn(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
@@ -240,6 +286,9 @@ def decompress(s, shape, out=None, err=None, stream=None, dtype=None, global_lor
     import torch
 
     dims = dims_of(shape)
+    _check_buffer(s, "s", (torch.uint8,), 256, header_bytes(shape))
+    if err is not None:
+        _check_buffer(err, "err", (torch.int32,), 4, 1)
     if dtype is None:
         dtype = out.dtype if out is not None else torch.float32
     if dtype not in (torch.float32, torch.float64):
@@ -256,14 +305,15 @@ def decompress(s, shape, out=None, err=None, stream=None, dtype=None, global_lor
         if work is None:  # freed when this returns: keep it until the launch's stream has passed it
             work = torch.empty(max(nwork, 16), dtype=torch.uint8, device=s.device)
             work.record_stream(stream if stream is not None else torch.cuda.current_stream())
-        elif work.numel() * work.element_size() < nwork or not work.is_cuda or not work.is_contiguous():
-            raise ValueError("work must be a CUDA tensor of at least %d bytes" % nwork)
-        rc = lib().fz_decompress_global(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        elif _nbytes(work) < nwork or not work.is_cuda or not work.is_contiguous() or work.data_ptr() % 256:
+            raise ValueError("work must be a contiguous CUDA tensor of at least %d bytes on a 256-byte boundary"
+                             % nwork)
+        rc = lib().fz_decompress_global(ctypes.c_void_p(s.data_ptr()), _nbytes(s), ctypes.c_void_p(out.data_ptr()),
                                         ctypes.byref(dims), errp, ctypes.c_void_p(work.data_ptr()),
                                         _stream_ptr(stream))
     else:
         fn = lib().fz_decompress_f64 if dtype == torch.float64 else lib().fz_decompress
-        rc = fn(ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims), errp,
+        rc = fn(ctypes.c_void_p(s.data_ptr()), _nbytes(s), ctypes.c_void_p(out.data_ptr()), ctypes.byref(dims), errp,
                 _stream_ptr(stream))
     if rc:
         raise FzError(rc, "fz_decompress")
@@ -392,8 +442,8 @@ class Batch:
             bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
             if out is None:
                 out = torch.empty(bound, dtype=torch.uint8, device=x.device)
-            elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
-                raise ValueError("job %d: out must be a uint8 CUDA tensor of at least %d bytes" % (i, bound))
+            else:
+                _check_buffer(out, "job %d: out" % i, (torch.uint8,), 256, bound)
             arr[i].d_in, arr[i].dims, arr[i].eb = x.data_ptr(), dims, float(eb)
             arr[i].eb_mode, arr[i].d_out = _mode(mode), out.data_ptr()
             keep += [x, out]
@@ -411,10 +461,16 @@ class Batch:
         arr = (FzDecompressJob * len(jobs))()
         keep, outs = [], []
         for i, (s, shape, out, err) in enumerate(jobs):
+            _check_buffer(s, "job %d: stream" % i, (torch.uint8,), 256, header_bytes(shape))
             if out is None:
                 out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
+            else:
+                _check_buffer(out, "job %d: out" % i, (torch.float32,), 4, math.prod(shape))
+            if err is not None:
+                _check_buffer(err, "job %d: err" % i, (torch.int32,), 4, 1)
             arr[i].d_stream, arr[i].dims, arr[i].d_out = s.data_ptr(), dims_of(shape), out.data_ptr()
             arr[i].d_err = err.data_ptr() if err is not None else None
+            arr[i].stream_bytes = _nbytes(s)
             keep += [s, out] + ([err] if err is not None else [])
             outs.append(out)
         h = ctypes.c_void_p()
@@ -462,11 +518,19 @@ class Server:
         self._live = {}
 
     def _submit(self, req, keep, out):
+        import torch
+
+        # the request's kernels wait (on the device) for what the current
+        # stream has enqueued so far: the producer of the input, and any
+        # earlier use of the output's memory
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        req.ready_event = ev.cuda_event
         t = ctypes.c_uint64()
         rc = lib().fz_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
         if rc:
             raise FzError(rc, "fz_server_submit")
-        self._live[t.value] = (keep, out)
+        self._live[t.value] = (keep + [ev], out)
         return t.value
 
     def submit_compress(self, x, eb, mode="rel", out=None, hbm_bytes=0):
@@ -478,8 +542,8 @@ class Server:
         bound = int(lib().fz_compress_bound(ctypes.byref(dims)))
         if out is None:
             out = torch.empty(bound, dtype=torch.uint8, device=x.device)
-        elif out.numel() < bound or out.dtype != torch.uint8 or not out.is_cuda:
-            raise ValueError("out must be a uint8 CUDA tensor of at least %d bytes" % bound)
+        else:
+            _check_buffer(out, "out", (torch.uint8,), 256, bound)
         r = FzRequest(kind=FZ_REQ_COMPRESS, eb_mode=_mode(mode), eb=float(eb), dims=dims, d_in=x.data_ptr(),
                       d_out=out.data_ptr(), d_err=None, hbm_bytes=int(hbm_bytes))
         return self._submit(r, [x, out], out)
@@ -487,11 +551,16 @@ class Server:
     def submit_decompress(self, s, shape, out=None, err=None, hbm_bytes=0):
         import torch
 
+        _check_buffer(s, "s", (torch.uint8,), 256, header_bytes(shape))
         if out is None:
             out = torch.empty(tuple(shape), dtype=torch.float32, device=s.device)
+        else:
+            _check_buffer(out, "out", (torch.float32,), 4, math.prod(shape))
+        if err is not None:
+            _check_buffer(err, "err", (torch.int32,), 4, 1)
         r = FzRequest(kind=FZ_REQ_DECOMPRESS, eb_mode=0, eb=0.0, dims=dims_of(shape), d_in=s.data_ptr(),
                       d_out=out.data_ptr(), d_err=err.data_ptr() if err is not None else None,
-                      hbm_bytes=int(hbm_bytes))
+                      hbm_bytes=int(hbm_bytes), stream_bytes=_nbytes(s))
         return self._submit(r, [s, out, err], out)
 
     def wait(self, ticket):

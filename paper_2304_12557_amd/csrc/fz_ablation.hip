@@ -6,8 +6,9 @@
 // multiples of the 16x32x64 chunk box, in the product's code geometry: a step
 // is one z-plane (32 x 64) of a chunk, cut into 64 patches of 4 rows x 8
 // columns.
-//   pred-quant v1 : the original dual-quantization (Sec. 2.3): q = rint(x/2eb),
-//                   chunk-local Lorenzo delta d; a code q' = d + r for -r < d < r,
+//   pred-quant v1 : the original dual-quantization (Sec. 2.3): q = rint(x * inv)
+//                   with inv = fp32(1 / (2 eb)) (one fp32 multiply, as the
+//                   product's prequantization), chunk-local Lorenzo delta d; a code q' = d + r for -r < d < r,
 //                   else code 0 and d written to a dense outlier array of one
 //                   int32 per value (r = 512).
 //   pred-quant v2 : the optimized one (Sec. 3.2): no shift, no outlier

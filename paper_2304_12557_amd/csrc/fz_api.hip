@@ -111,23 +111,46 @@ size_t fz_header_bytes(const fz_dims* dims)
     return (size_t)g.payload_off;
 }
 
-int fz_compress(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
+int fz_compress_timed(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream,
+                      const fz_timing* timing)
 {
     Geom g;
-    if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    if (!d_in || !d_out || !geom_of(dims, &g) || !aligned_to(d_in, 4) || !aligned_to(d_out, 256)) return FZ_ERR_ARG;
     float ebx2 = 0.0f, inv = 0.0f;
     const int rc = bound_params(eb, eb_mode, &ebx2, &inv);
     if (rc != FZ_OK) return rc;
     const HeaderImage h = header_image(g, eb, eb_mode, ebx2, inv);
-    hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb, static_cast<hipStream_t>(stream));
+    Timing t{};
+    if (timing) {
+        t.range_begin = static_cast<hipEvent_t>(timing->range_begin);
+        t.main_begin = static_cast<hipEvent_t>(timing->main_begin);
+        t.main_end = static_cast<hipEvent_t>(timing->main_end);
+        t.done = static_cast<hipEvent_t>(timing->done);
+    }
+    hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb,
+                                   static_cast<hipStream_t>(stream), timing ? &t : nullptr);
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
-int fz_decompress(const void* d_stream, float* d_out, const fz_dims* dims, uint32_t* d_err, void* stream)
+int fz_compress(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
+{
+    return fz_compress_timed(d_in, dims, eb, eb_mode, d_out, stream, nullptr);
+}
+
+// the checks every decompression entry point makes on its arguments
+static bool decompress_args(const void* d_stream, size_t stream_bytes, const void* d_out, size_t align_out,
+                            const fz_dims* dims, const uint32_t* d_err, Geom* g)
+{
+    return d_stream && d_out && geom_of(dims, g) && aligned_to(d_stream, 256) && aligned_to(d_out, align_out) &&
+           aligned_to(d_err, 4) && stream_bytes >= (size_t)g->payload_off;
+}
+
+int fz_decompress(const void* d_stream, size_t stream_bytes, float* d_out, const fz_dims* dims, uint32_t* d_err,
+                  void* stream)
 {
     Geom g;
-    if (!d_stream || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
-    hipError_t e = launch_decompress(static_cast<const uint8_t*>(d_stream), d_out, g, d_err,
+    if (!decompress_args(d_stream, stream_bytes, d_out, 4, dims, d_err, &g)) return FZ_ERR_ARG;
+    hipError_t e = launch_decompress(static_cast<const uint8_t*>(d_stream), stream_bytes, d_out, g, d_err,
                                      static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
@@ -142,7 +165,7 @@ size_t fz_compress_bound_f64(const fz_dims* dims)
 int fz_compress_f64(const double* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
 {
     Geom g;
-    if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    if (!d_in || !d_out || !geom_of(dims, &g) || !aligned_to(d_in, 8) || !aligned_to(d_out, 256)) return FZ_ERR_ARG;
     if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != FZ_EB_ABS && eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
     double ebx2 = 0.0, inv = 0.0;  // REL: derived on the device
     if (eb_mode == FZ_EB_ABS) {
@@ -156,11 +179,12 @@ int fz_compress_f64(const double* d_in, const fz_dims* dims, double eb, int eb_m
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 
-int fz_decompress_f64(const void* d_stream, double* d_out, const fz_dims* dims, uint32_t* d_err, void* stream)
+int fz_decompress_f64(const void* d_stream, size_t stream_bytes, double* d_out, const fz_dims* dims, uint32_t* d_err,
+                      void* stream)
 {
     Geom g;
-    if (!d_stream || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
-    hipError_t e = launch_decompress_f64(static_cast<const uint8_t*>(d_stream), d_out, g, d_err,
+    if (!decompress_args(d_stream, stream_bytes, d_out, 8, dims, d_err, &g)) return FZ_ERR_ARG;
+    hipError_t e = launch_decompress_f64(static_cast<const uint8_t*>(d_stream), stream_bytes, d_out, g, d_err,
                                          static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
@@ -175,7 +199,7 @@ size_t fz_compress_bound_global(const fz_dims* dims)
 int fz_compress_global(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream)
 {
     Geom g;
-    if (!d_in || !d_out || !geom_of(dims, &g)) return FZ_ERR_ARG;
+    if (!d_in || !d_out || !geom_of(dims, &g) || !aligned_to(d_in, 4) || !aligned_to(d_out, 256)) return FZ_ERR_ARG;
     float ebx2 = 0.0f, inv = 0.0f;
     const int rc = bound_params(eb, eb_mode, &ebx2, &inv);
     if (rc != FZ_OK) return rc;
@@ -194,13 +218,14 @@ size_t fz_decompress_global_work_bytes(const fz_dims* dims)
     return global_work_bytes(g);
 }
 
-int fz_decompress_global(const void* d_stream, float* d_out, const fz_dims* dims, uint32_t* d_err, void* d_work,
-                         void* stream)
+int fz_decompress_global(const void* d_stream, size_t stream_bytes, float* d_out, const fz_dims* dims,
+                         uint32_t* d_err, void* d_work, void* stream)
 {
     Geom g;
-    if (!d_stream || !d_out || !d_work || !geom_of(dims, &g)) return FZ_ERR_ARG;
-    hipError_t e = launch_decompress_global(static_cast<const uint8_t*>(d_stream), d_out, g, d_err, d_work,
-                                            static_cast<hipStream_t>(stream));
+    if (!decompress_args(d_stream, stream_bytes, d_out, 4, dims, d_err, &g) || !d_work || !aligned_to(d_work, 256))
+        return FZ_ERR_ARG;
+    hipError_t e = launch_decompress_global(static_cast<const uint8_t*>(d_stream), stream_bytes, d_out, g, d_err,
+                                            d_work, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 

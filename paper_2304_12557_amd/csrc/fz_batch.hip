@@ -4,9 +4,10 @@
 // A plan holds, in device memory, one descriptor per field and a chunk -> field
 // table over the concatenated chunks of all fields.  Running a compression
 // plan enqueues a fixed sequence of launches whatever the number of fields:
-//   init (all fields) -> value range + eb (REL fields) -> ONE persistent
-//   compression launch over every chunk of every field -> prefix sum (one
-//   workgroup per field) -> placement copy (all chunks)
+//   init (all fields) -> value range + eb (REL fields) -> one persistent
+//   compression launch per (rank, row-alignment) class present (at most six,
+//   usually three), each over every chunk of every field of its class ->
+//   prefix sum (one workgroup per field) -> placement copy (all chunks)
 // and a decompression plan one launch over every chunk of every field.  Each
 // field's bytes are exactly those of the per-field call: the per-chunk and
 // per-field device code is the same (fz_compress_dev.hpp,
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
                 loaded = true;
             }
         }
-        if (!skip) chunk_place(J.out, g, c, wave, lane, F, myflag, nout, S);
+        if (!skip) chunk_place<RANK, VEC4>(J.x, J.out, g, c, wave, lane, inv, F, myflag, nout, S);
         if (tn >= total) break;
         t = tn;
         j = jn;
@@ -145,12 +146,12 @@ __global__ __launch_bounds__(64) void k_batch_decompress(const DecompressJob* __
     const int64_t c = (int64_t)blockIdx.x - J.chunk0;
     const int lane = threadIdx.x;
     switch (J.key) {
-        case 7: decompress_chunk_any<3, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 6: decompress_chunk_any<3, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 5: decompress_chunk_any<2, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 4: decompress_chunk_any<2, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        case 3: decompress_chunk_any<1, true>(J.s, J.y, J.g, J.err, c, lane, tile); break;
-        default: decompress_chunk_any<1, false>(J.s, J.y, J.g, J.err, c, lane, tile); break;
+        case 7: decompress_chunk_any<3, true>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
+        case 6: decompress_chunk_any<3, false>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
+        case 5: decompress_chunk_any<2, true>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
+        case 4: decompress_chunk_any<2, false>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
+        case 3: decompress_chunk_any<1, true>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
+        default: decompress_chunk_any<1, false>(J.s, J.s_bytes, J.y, J.g, J.err, c, lane, tile); break;
     }
 }
 
@@ -306,6 +307,7 @@ int plan_compress(Plan* Pp, int n, const fz_compress_job* jobs)
         std::memset(&J, 0, sizeof(J));
         const double eb = q.eb;
         if (!q.d_in || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) return FZ_ERR_ARG;
+        if (!aligned_to(q.d_in, 4) || !aligned_to(q.d_out, 256)) return FZ_ERR_ARG;
         if (!(eb > 0.0) || !std::isfinite(eb) || (q.eb_mode != FZ_EB_ABS && q.eb_mode != FZ_EB_REL)) return FZ_ERR_ARG;
         float ebx2 = 0.0f, inv = 0.0f;
         if (q.eb_mode == FZ_EB_ABS && !abs_params(eb, &ebx2, &inv)) return FZ_ERR_EB_RANGE;
@@ -353,7 +355,11 @@ int plan_decompress(Plan* Pp, int n, const fz_decompress_job* jobs)
         DecompressJob J;
         std::memset(&J, 0, sizeof(J));
         if (!q.d_stream || !q.d_out || !make_geom((int)q.dims.rank, q.dims.n, &J.g)) return FZ_ERR_ARG;
+        if (!aligned_to(q.d_stream, 256) || !aligned_to(q.d_out, 4) || !aligned_to(q.d_err, 4) ||
+            q.stream_bytes < (uint64_t)J.g.payload_off)
+            return FZ_ERR_ARG;
         J.s = static_cast<const uint8_t*>(q.d_stream);
+        J.s_bytes = q.stream_bytes;
         J.y = q.d_out;
         J.err = q.d_err;
         J.key = vec_key(q.d_out, J.g);

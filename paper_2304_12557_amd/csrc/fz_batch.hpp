@@ -36,6 +36,7 @@ struct DecompressJob {
     int32_t key;
     int32_t pad;
     int64_t chunk0;
+    uint64_t s_bytes;  // bytes readable at s
 };
 
 struct Tuning {

@@ -52,10 +52,10 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
             l = lane_geo<RANK>(g, cn, lane);
             if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         }
-        chunk_place(out, g, c, wave, lane, F, myflag, nout, S);
+        chunk_place<RANK, VEC4, QM>(x, out, g, c, wave, lane, inv, F, myflag, nout, S);
         if (cn >= g.n_chunks) break;
         c = cn;
-        __syncthreads();  // the LDS counts and logs are reused by the next chunk
+        __syncthreads();  // the LDS counts and bricks are reused by the next chunk
     }
 }
 
@@ -87,8 +87,10 @@ int64_t minmax_blocks(int64_t n)
     return blocks < 1 ? 1 : blocks;
 }
 
+static hipError_t mark(hipEvent_t e, hipStream_t st) { return e ? hipEventRecord(e, st) : hipSuccess; }
+
 template <int RANK, bool VEC4, int QM>
-static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st)
+static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st, const Timing* t = nullptr)
 {
     // persistent grid: as many workgroups as stay resident, at most one per chunk
     int dev = 0, cus = 0, per_cu = 0;
@@ -99,13 +101,16 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
         per_cu = 1;
     const int64_t resident = (int64_t)cus * per_cu;
     const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
+    hipError_t e;
+    if (t && (e = mark(t->main_begin, st)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t && (e = mark(t->main_end, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, out, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_move, dim3((unsigned)g.n_chunks), dim3(256), 0, st, out, g);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return t ? mark(t->done, st) : hipSuccess;
 }
 
 static hipError_t launch_init(uint8_t* out, const Geom& g, const HeaderImage& h, hipStream_t st)
@@ -164,10 +169,11 @@ hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, c
 }
 
 hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
-                           hipStream_t st)
+                           hipStream_t st, const Timing* t)
 {
     hipError_t e = launch_init(out, g, h, st);
     if (e != hipSuccess) return e;
+    if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
     if (mode == FZ_EB_REL) {
         const int64_t n = g.n[0] * g.n[1] * g.n[2];
         const int64_t blocks = minmax_blocks(n);
@@ -179,21 +185,21 @@ hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const He
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     if (mode == FZ_EB_PWREL) {
         switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-            case 7: return launch_rank<3, true, kQuantPw>(x, out, g, st);
-            case 6: return launch_rank<3, false, kQuantPw>(x, out, g, st);
-            case 5: return launch_rank<2, true, kQuantPw>(x, out, g, st);
-            case 4: return launch_rank<2, false, kQuantPw>(x, out, g, st);
-            case 3: return launch_rank<1, true, kQuantPw>(x, out, g, st);
-            default: return launch_rank<1, false, kQuantPw>(x, out, g, st);
+            case 7: return launch_rank<3, true, kQuantPw>(x, out, g, st, t);
+            case 6: return launch_rank<3, false, kQuantPw>(x, out, g, st, t);
+            case 5: return launch_rank<2, true, kQuantPw>(x, out, g, st, t);
+            case 4: return launch_rank<2, false, kQuantPw>(x, out, g, st, t);
+            case 3: return launch_rank<1, true, kQuantPw>(x, out, g, st, t);
+            default: return launch_rank<1, false, kQuantPw>(x, out, g, st, t);
         }
     }
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true, kQuantGrid>(x, out, g, st);
-        case 6: return launch_rank<3, false, kQuantGrid>(x, out, g, st);
-        case 5: return launch_rank<2, true, kQuantGrid>(x, out, g, st);
-        case 4: return launch_rank<2, false, kQuantGrid>(x, out, g, st);
-        case 3: return launch_rank<1, true, kQuantGrid>(x, out, g, st);
-        default: return launch_rank<1, false, kQuantGrid>(x, out, g, st);
+        case 7: return launch_rank<3, true, kQuantGrid>(x, out, g, st, t);
+        case 6: return launch_rank<3, false, kQuantGrid>(x, out, g, st, t);
+        case 5: return launch_rank<2, true, kQuantGrid>(x, out, g, st, t);
+        case 4: return launch_rank<2, false, kQuantGrid>(x, out, g, st, t);
+        case 3: return launch_rank<1, true, kQuantGrid>(x, out, g, st, t);
+        default: return launch_rank<1, false, kQuantGrid>(x, out, g, st, t);
     }
 }
 

@@ -10,7 +10,10 @@
 // registers (the bitshuffle of Sec. 3.3).  After its 4 steps a lane holds 16
 // bricks (one per bit plane); a ballot per plane gives the bit flags of the
 // zero-block encoder (Sec. 3.4), and the nonzero bricks are compacted into
-// the chunk's staging slot with coalesced 16-byte writes.
+// the chunk's staging slot with coalesced 16-byte writes.  A layer whose
+// deltas need escapes is computed again out of line; its (index, delta) pairs
+// are written after the workgroup barrier, once every layer's count is known,
+// straight to their place behind the chunk's bricks.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,9 +24,9 @@
 namespace fz {
 
 struct EscapeLog {
-    uint32_t* idx;  // LDS, kLayerOutlierCap entries for this wave
-    int32_t* val;
-    int count;      // escapes seen so far in this layer (may exceed the cap)
+    uint32_t* pairs;  // null: count only; else the layer's (index, delta) pairs in the payload
+    int count;        // escapes seen so far in this layer
+    int room;         // pairs that may be written (what the chunk's allowance leaves the layer)
 };
 
 // Slow path of a step with at least one escape: codes whose delta does not
@@ -41,10 +44,8 @@ __device__ __forceinline__ void log_escapes(const int (&d)[32], uint32_t (&P)[16
 #pragma unroll
     for (int i = 0; i < 32; i++) {
         if ((emask >> i) & 1u) {
-            if (pos < kLayerOutlierCap) {
-                log.idx[pos] = n0 + (uint32_t)lane * kPatchCodes + i;
-                log.val[pos] = d[i];
-            }
+            if (log.pairs && pos < log.room)
+                *reinterpret_cast<uint2*>(log.pairs + 2 * pos) = make_uint2(n0 + (uint32_t)lane * kPatchCodes + i, (uint32_t)d[i]);
             pos++;
         }
     }
@@ -171,9 +172,12 @@ __device__ __forceinline__ const float* step_base(const float* __restrict__ x, c
 }
 
 // load the lane's 32 values of step s (s = 4k-1 is the halo of layer k).
-// In a chunk cut by the field's edge every index is clamped into the field:
-// cells outside it then hold some in-field value, and their deltas are zeroed
-// later (a delta inside the field never looks at a cell outside it).
+// In a chunk cut by the field's edge, cells outside the field hold 0 (rows
+// whose 16-byte pieces are whole vectors: through a buffer resource whose
+// range ends at the chunk's last in-field value, with an offset past it for
+// the pieces outside the field) or a clamped in-field value (other rows);
+// either way their deltas are zeroed later (a delta inside the field never
+// looks at a cell outside it).
 // 3-D interior loads are nontemporal except for the top step of a layer
 // (s mod 4 = 3), which the next layer's wave reads again as its halo in the
 // same iteration and must find in the cache (measured: the 512^3 ABS
@@ -188,7 +192,24 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
     const float* b = step_base<RANK>(x, g, l, s);
     if (RANK == 3) {
         const int64_t nx = g.n[2];
-        if (EDGE) {
+        if (EDGE && VEC4 && 32 * 4 * nx < 0x80000000ll) {  // uniform; ext[2] is a multiple of 4 here
+            const int py = lane & 7, px = lane >> 3;
+            const uint32_t rows = (uint32_t)l.ext[1], cols = (uint32_t)l.ext[2];
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(b), (short)0, (int)(4u * ((rows - 1) * (uint32_t)nx + cols)), kBufferFlags);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t row = 4u * py + r;
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const uint32_t col = 8u * px + 4u * j;
+                    const uint32_t voff = row < rows && col < cols ? 4u * (row * (uint32_t)nx + col) : 0x80000000u;
+                    const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0u, 0);
+                    v[8 * r + 4 * j] = __uint_as_float(t.x); v[8 * r + 4 * j + 1] = __uint_as_float(t.y);
+                    v[8 * r + 4 * j + 2] = __uint_as_float(t.z); v[8 * r + 4 * j + 3] = __uint_as_float(t.w);
+                }
+            }
+        } else if (EDGE) {
             const int py = lane & 7, px = lane >> 3;
             const int ey = (int)l.ext[1] - 1, ex = (int)l.ext[2] - 1;
 #pragma unroll
@@ -209,7 +230,23 @@ __device__ __forceinline__ void load_step(const float* __restrict__ x, const Geo
         }
     } else if (RANK == 2) {
         const int64_t nx = g.n[1];
-        if (EDGE) {
+        if (EDGE && VEC4 && 2 * 4 * nx < 0x80000000ll) {  // uniform; ext[1] is a multiple of 4 here
+            const uint32_t rows = (uint32_t)min((int64_t)2, l.ext[0] - 2 * s), cols = (uint32_t)l.ext[1];
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(b), (short)0, (int)(4u * ((rows - 1) * (uint32_t)nx + cols)), kBufferFlags);
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t col = 16u * lane + 4u * j;
+                    const uint32_t voff = (uint32_t)r < rows && col < cols ? 4u * ((uint32_t)r * (uint32_t)nx + col)
+                                                                            : 0x80000000u;
+                    const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0u, 0);
+                    v[16 * r + 4 * j] = __uint_as_float(t.x); v[16 * r + 4 * j + 1] = __uint_as_float(t.y);
+                    v[16 * r + 4 * j + 2] = __uint_as_float(t.z); v[16 * r + 4 * j + 3] = __uint_as_float(t.w);
+                }
+            }
+        } else if (EDGE) {
             const int ex = (int)l.ext[1] - 1;
             const int64_t last = l.ext[0] - 1 - 2 * s;  // last field row relative to the step
 #pragma unroll
@@ -497,16 +534,17 @@ __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom
 }
 
 // Out-of-line layer pass for the uncommon cases: a chunk cut by the field's
-// edge, or a layer whose deltas need escapes (computed again with logging).
-// It loads its own inputs, writes the layer's bricks to Wl and returns
-// (escape count << 32) | max-|p| bits.  The geometry is read from the copy
+// edge, or a layer whose deltas need escapes (computed again with the escape
+// codes).  It loads its own inputs, writes the layer's bricks to Wl, logs the
+// escape pairs to `pairs` (at most `room` of them; null: count only) and
+// returns (escape count << 32) | max-|p| bits.  The geometry is read from the copy
 // in the scratch so that nothing large crosses the call.  It stays a real
 // call: inlined, its registers would push the fast path into spills, while
 // as a call the register saves happen only on this path.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
-                                            int64_t c, int k, Quant inv, int lane, uint32_t* Wl, uint32_t* oidx,
-                                            int32_t* oval)
+                                            int64_t c, int k, Quant inv, int lane, uint32_t* Wl, uint32_t* pairs,
+                                            int room)
 {
     const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
     const Lane l = lane_geo<RANK>(g, c, lane);
@@ -514,7 +552,7 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
     prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
     uint32_t nz[16];
     float facc = 0.0f;
-    EscapeLog log{oidx, oval, 0};
+    EscapeLog log{pairs, 0, room};
     if (l.edge) layer<RANK, true, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     else layer<RANK, false, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     return ((uint64_t)(uint32_t)log.count << 32) | __float_as_uint(facc);
@@ -553,14 +591,12 @@ struct CompressLds {
     uint32_t err;
     uint32_t nnz[kLayers], nout[kLayers];
     uint64_t ticket;
-    uint32_t oidx[kLayers][kLayerOutlierCap];
-    int32_t oval[kLayers][kLayerOutlierCap];
     // per wave: the bricks of its layer (as plane-step words)
     uint32_t w[kLayers][kPlanes * 4 * 64];
 };
 
 // Tail of a wave's layer: the data-dependent status bits (NaN/Inf or an
-// overflowing product, seen in facc; too many escapes), the flags of the
+// overflowing product, seen in facc), the flags of the
 // zero-block encoder (one ballot per bit plane, F; lane b < 16 gets F[b] in
 // `myflag`, which chunk_place stores), and the layer's counts in S.  Returns
 // the layer's escape count.
@@ -575,8 +611,7 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 #pragma unroll
         for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
     }
-    if (log.count > kLayerOutlierCap) err |= kErrOutlierCap;
-    const int nout = log.count < kLayerOutlierCap ? log.count : kLayerOutlierCap;
+    const int nout = log.count;
 
     // flags of the zero-block encoder: one ballot per bit plane
     uint32_t nnz = 0;
@@ -595,11 +630,11 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
     return nout;
 }
 
-// Wave `wave`'s layer of chunk c: bricks into S.w[wave], escapes into its
-// log, its counts into S.  `h` / `v` hold the prefetched halo and first step
+// Wave `wave`'s layer of chunk c: bricks into S.w[wave], its brick and
+// escape counts into S.  `h` / `v` hold the prefetched halo and first step
 // unless the chunk is cut by the field's edge (the out-of-line pass then
 // loads its own).  F receives the layer's per-plane ballots and `myflag` the
-// flag word lane b < 16 stores; returns the layer's logged escape count.
+// flag word lane b < 16 stores; returns the layer's escape count.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
                                            int64_t c, const Lane& l, int wave, int lane, Quant inv, float (&h)[32],
@@ -608,7 +643,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
     uint32_t nz[16];
     float facc = 0.0f;
     uint32_t* Wl = S.w[wave];
-    EscapeLog log{S.oidx[wave], S.oval[wave], 0};
+    EscapeLog log{nullptr, 0, 0};
     if (wave < l.L) {
         bool slow = l.edge;
         if (!slow) {
@@ -621,7 +656,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
             }
         }
         if (slow) {  // edge chunk, or escapes to log
-            const uint64_t r = layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, log.idx, log.val);
+            const uint64_t r = layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, nullptr, 0);
             log.count = (int)(r >> 32);
             facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
 #pragma unroll
@@ -642,29 +677,38 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
 // placement kernels turn the sizes into offsets), its escape count to the
 // table, the counts to the header, and its payload is assembled in its
 // staging slot: nonzero bricks in (layer, plane, patch) order, then the
-// escape pairs padded to 16 bytes.
-__device__ __forceinline__ void chunk_place(uint8_t* __restrict__ out, const Geom& g, int64_t c, int wave, int lane,
-                                            const uint64_t (&F)[16], uint64_t myflag, int nout, CompressLds& S)
+// escape pairs padded to 16 bytes.  A chunk may hold kChunkOutlierCap
+// escapes wherever they fall; past that the stream carries the OUTLIER_CAP
+// status and no pairs are written.  A layer with escapes is computed again
+// out of line (its first pass kept only the count) and writes its pairs
+// behind those of the layers before it.
+template <int RANK, bool VEC4, int QM = kQuantGrid>
+__device__ __forceinline__ void chunk_place(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+                                            int64_t c, int wave, int lane, Quant inv, const uint64_t (&F)[16],
+                                            uint64_t myflag, int nout, CompressLds& S)
 {
     if (lane < 16)
         reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
     uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
     const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
-    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];
+    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];  // each at most 8192: no overflow
+    const bool capped = to > (uint32_t)kChunkOutlierCap;
+    const uint32_t kept = capped ? 0u : to;
     uint8_t* slot = out + g.stage_off + kStageSlotBytes * c;
     if (threadIdx.x == 0) {
-        const uint64_t units = tn + (to + 1) / 2;
+        const uint64_t units = tn + (kept + 1) / 2;
         state[c] = kFlagAgg | units;
-        reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[1] = to;
+        reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[1] = kept;
         atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
-        atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)to);
-        if (S.err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), S.err);
+        atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)kept);
+        const uint32_t err = S.err | (capped ? kErrOutlierCap : 0u);
+        if (err) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), err);
         S.err = 0;
-        if (to & 1u) *reinterpret_cast<uint2*>(slot + 16 * tn + 8 * to) = make_uint2(0u, 0u);
+        if (kept & 1u) *reinterpret_cast<uint2*>(slot + 16 * tn + 8 * kept) = make_uint2(0u, 0u);
     }
     uint64_t base = 0;
     for (int w = 0; w < wave; w++) base += S.nnz[w];
-    const uint32_t* Wl = S.w[wave];
+    uint32_t* Wl = S.w[wave];
 #pragma unroll
     for (int b = 0; b < 16; b++) {
         if (F[b] == 0) continue;  // uniform: a bit plane without nonzero bricks
@@ -675,14 +719,11 @@ __device__ __forceinline__ void chunk_place(uint8_t* __restrict__ out, const Geo
         }
         base += __popcll(F[b]);
     }
-    if (nout) {
+    if (nout && !capped) {  // rare: this layer's escape pairs, in code-index order
         uint32_t first = 0;
         for (int w = 0; w < wave; w++) first += S.nout[w];
-        uint32_t* pairs = reinterpret_cast<uint32_t*>(slot + 16 * tn);
-        for (int i = lane; i < nout; i += 64) {
-            pairs[2 * (first + i)] = S.oidx[wave][i];
-            pairs[2 * (first + i) + 1] = (uint32_t)S.oval[wave][i];
-        }
+        uint32_t* pairs = reinterpret_cast<uint32_t*>(slot + 16 * tn) + 2 * first;
+        (void)layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, pairs, nout);
     }
 }
 

@@ -8,11 +8,11 @@
 namespace fz {
 
 template <int RANK, bool VEC4>
-__global__ __launch_bounds__(64) void k_decompress(const uint8_t* __restrict__ s, float* __restrict__ y, Geom g,
-                                                   uint32_t* d_err)
+__global__ __launch_bounds__(64) void k_decompress(const uint8_t* __restrict__ s, uint64_t sb, float* __restrict__ y,
+                                                   Geom g, uint32_t* d_err)
 {
     __shared__ float tile[kTileFloats];
-    decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
+    decompress_chunk_any<RANK, VEC4>(s, sb, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v)
@@ -21,13 +21,13 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v)
 }
 
 template <int RANK, bool VEC4>
-static hipError_t launch_rank(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st)
+static hipError_t launch_rank(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_decompress<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, y, g, d_err);
+    hipLaunchKernelGGL((k_decompress<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, sb, y, g, d_err);
     return hipGetLastError();
 }
 
-hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st)
+hipError_t launch_decompress(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err, hipStream_t st)
 {
     if (d_err) {
         hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, st, d_err, 0u);
@@ -36,12 +36,12 @@ hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t
     }
     const bool vec4 = (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true>(s, y, g, d_err, st);
-        case 6: return launch_rank<3, false>(s, y, g, d_err, st);
-        case 5: return launch_rank<2, true>(s, y, g, d_err, st);
-        case 4: return launch_rank<2, false>(s, y, g, d_err, st);
-        case 3: return launch_rank<1, true>(s, y, g, d_err, st);
-        default: return launch_rank<1, false>(s, y, g, d_err, st);
+        case 7: return launch_rank<3, true>(s, sb, y, g, d_err, st);
+        case 6: return launch_rank<3, false>(s, sb, y, g, d_err, st);
+        case 5: return launch_rank<2, true>(s, sb, y, g, d_err, st);
+        case 4: return launch_rank<2, false>(s, sb, y, g, d_err, st);
+        case 3: return launch_rank<1, true>(s, sb, y, g, d_err, st);
+        default: return launch_rank<1, false>(s, sb, y, g, d_err, st);
     }
 }
 

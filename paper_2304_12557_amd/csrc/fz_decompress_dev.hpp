@@ -21,9 +21,11 @@
 namespace fz {
 
 // dtype: 0 for an fp32 output, 1 for fp64; predictor: the header byte 15
-// the caller handles (0 chunk-local Lorenzo, 1 field-global)
+// the caller handles (0 chunk-local Lorenzo, 1 field-global); s_bytes: the
+// bytes readable at s (at least the header, table and flags, checked on the
+// host)
 __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank, int dtype,
-                                                 int predictor)
+                                                 int predictor, uint64_t s_bytes)
 {
     const uint32_t w0 = *reinterpret_cast<const uint32_t*>(s + kOffMagic);
     const uint32_t w1 = *reinterpret_cast<const uint32_t*>(s + kOffVersion);
@@ -44,7 +46,7 @@ __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, 
         if (reinterpret_cast<const uint64_t*>(s + kOffDims)[i] != (uint64_t)g.n[i]) return 6;
     if (*reinterpret_cast<const uint32_t*>(s + kOffNChunks) != (uint32_t)g.n_chunks) return 6;
     const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
-    if (total < (uint64_t)g.payload_off || ((total - g.payload_off) & 15) != 0) return 6;
+    if (total < (uint64_t)g.payload_off || ((total - g.payload_off) & 15) != 0 || total > s_bytes) return 6;
     return 0;
 }
 
@@ -146,7 +148,8 @@ __device__ __forceinline__ void store_run_masked(T* __restrict__ p, const int* q
 // Decompress chunk c of a field with one wave (lane = 0..63; the workgroup is
 // that one wave).  `tile` is kTileFloats of LDS.  A stream that fails a check
 // writes an fz_status code to *d_err (if given) and leaves the chunk's output
-// untouched.
+// untouched.  No byte at or past s + s_bytes is read: the header's total is
+// checked against s_bytes, and every chunk's payload against the total.
 // LDS tile of one step: 3-D, 32 rows of 64 values with a row pitch of 68;
 // 2-D and 1-D, the step's 2048 values in order with 4 floats of padding after
 // every 32 (both paddings spread a wave's 16-byte accesses over the banks)
@@ -170,6 +173,27 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, u
         const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
         const uint32_t soff = (uint32_t)(i >> 2) * row_bytes + 1024u * (uint32_t)(i & 3);
         __builtin_amdgcn_raw_buffer_store_b128(w, rs, 16u * (uint32_t)lane, soff, kCacheStreamStore);
+    }
+    __syncthreads();  // the tile is rewritten by the next step
+}
+
+// The same for a 2-D step of a chunk cut by the field's edge: `rows` (1 or
+// 2) rows of `cols` values (a multiple of 4) from `base`, row pitch `nx`
+// values; pieces outside the field are dropped by the resource's range
+// (offset past it), and the stores are plain, as the lines are partly written.
+__device__ __forceinline__ void store_tile_runs_edge(const float* tile, void* base, uint32_t nx, uint32_t rows,
+                                                     uint32_t cols, int lane)
+{
+    __syncthreads();  // one wave: orders the tile's writes before its reads
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(4u * ((rows - 1) * nx + cols)), kBufferFlags);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const float4 v = *reinterpret_cast<const float4*>(tile + run_slot(256 * i + 4 * lane));
+        const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+        const uint32_t row = (uint32_t)(i >> 2), col = 256u * (uint32_t)(i & 3) + 4u * (uint32_t)lane;
+        const uint32_t voff = row < rows && col < cols ? 4u * (row * nx + col) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 0u, 0);
     }
     __syncthreads();  // the tile is rewritten by the next step
 }
@@ -204,12 +228,12 @@ __device__ __forceinline__ void store_tile_runs64(const double* tile, double* ba
 }
 
 template <int RANK, bool VEC4, bool PW, typename T>
-__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, T* __restrict__ y, const Geom& g,
-                                                 uint32_t* d_err, int64_t c, int lane, float* tile)
+__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, uint64_t s_bytes, T* __restrict__ y,
+                                                 const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
 {
     constexpr bool F64 = sizeof(T) == 8;
     constexpr bool INT = std::is_integral_v<T>;
-    const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0, INT ? 1 : 0);
+    const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0, INT ? 1 : 0, s_bytes);
     if (hdr_err) {
         if (c == 0 && lane == 0 && d_err) atomicCAS(d_err, 0u, hdr_err);
         return;
@@ -228,7 +252,12 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     const int L = layers_of(RANK, ext[0]);
     uint32_t nnz = 0;
     for (int i = 0; i < kLayers * kPlanes; i++) nnz += __popcll(F[i]);
-    bool bad = nout > (uint32_t)kChunkOutlierCap || (uint64_t)off + nnz + (nout + 1) / 2 > payload_units;
+    // the table is the exclusive prefix sum of the chunks' units (Sec. 3.4):
+    // this chunk's offset plus its units (from the flags' popcounts and its
+    // escape count) is the next chunk's offset, or the payload's end; with
+    // chunk 0 at offset 0, every chunk lies inside the payload
+    const uint64_t next = c + 1 < g.n_chunks ? (uint64_t)tab[2] : payload_units;
+    bool bad = nout > (uint32_t)kChunkOutlierCap || (uint64_t)off + nnz + (nout + 1) / 2 != next || (c == 0 && off != 0);
     for (int i = L * kPlanes; i < kLayers * kPlanes; i++) bad |= F[i] != 0;
     if (bad) {
         if (lane == 0 && d_err) atomicCAS(d_err, 0u, 6u);
@@ -346,7 +375,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     carry3[i] = d[i];
                 }
                 const int64_t z = org[0] + st, y0 = org[1] + 4 * py, x0 = org[2] + 8 * px;
-                if (edge) {
+                if (edge && !(VEC4 && !F64 && 32 * 4 * g.n[2] < 0x80000000ll)) {
                     const int ey = clampi(ext[1] - 4 * py, 0, 4), ex = clampi(ext[2] - 8 * px, 0, 8);
 #pragma unroll
                     for (int r = 0; r < 4; r++)
@@ -366,18 +395,37 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                         tile_val<PW, T>(d[8 * r + 6], ebx2, step), tile_val<PW, T>(d[8 * r + 7], ebx2, step));
                     }
                     __syncthreads();  // one wave: orders the tile's writes before its reads
-                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                        y + (z * g.n[1] + org[1]) * g.n[2] + org[2], (short)0, -1, kBufferFlags);
-                    // offsets stay below 2^32: 32 rows of a contiguous extent below 2^25
-                    const uint32_t voff = 4u * ((uint32_t)(lane >> 4) * (uint32_t)g.n[2] + 4u * (lane & 15));
+                    T* plane = y + (z * g.n[1] + org[1]) * g.n[2] + org[2];
+                    if (!edge) {
+                        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(plane, (short)0, -1, kBufferFlags);
+                        // offsets stay below 2^32: 32 rows of a contiguous extent below 2^25
+                        const uint32_t voff = 4u * ((uint32_t)(lane >> 4) * (uint32_t)g.n[2] + 4u * (lane & 15));
 #pragma unroll
-                    for (int i = 0; i < 8; i++) {
-                        const float4 v = *reinterpret_cast<const float4*>(tile + (4 * i + (lane >> 4)) * kTilePitch +
-                                                                          4 * (lane & 15));
-                        const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
-                                            __float_as_uint(v.w)};
-                        __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2],
-                                                               kCacheStreamStore);
+                        for (int i = 0; i < 8; i++) {
+                            const float4 v = *reinterpret_cast<const float4*>(tile + (4 * i + (lane >> 4)) * kTilePitch +
+                                                                              4 * (lane & 15));
+                            const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                                __float_as_uint(v.w)};
+                            __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 16u * (uint32_t)i * (uint32_t)g.n[2],
+                                                                   kCacheStreamStore);
+                        }
+                    } else {
+                        // a chunk cut by the field's edge (its rows hold whole 16-byte pieces): the
+                        // pieces outside the field get an offset past the resource's range, where
+                        // the store is dropped; plain stores, as the rows' lines are partly written
+                        const uint32_t rows = (uint32_t)ext[1], cols = (uint32_t)ext[2], nx = (uint32_t)g.n[2];
+                        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                            plane, (short)0, (int)(4u * ((rows - 1) * nx + cols)), kBufferFlags);
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            const float4 v = *reinterpret_cast<const float4*>(tile + (4 * i + (lane >> 4)) * kTilePitch +
+                                                                              4 * (lane & 15));
+                            const fz_u32x4 w = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                                __float_as_uint(v.w)};
+                            const uint32_t row = 4u * i + (lane >> 4), col = 4u * (lane & 15);
+                            const uint32_t voff = row < rows && col < cols ? 4u * (row * nx + col) : 0x80000000u;
+                            __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 0u, 0);
+                        }
                     }
                     __syncthreads();  // the tile is rewritten by the next step
                 } else if constexpr (VEC4 && F64) {
@@ -424,7 +472,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                     carry2[cc] = d[16 + cc];
                 }
                 const int64_t yy = org[0] + 2 * st, x0 = org[1] + 16 * lane;
-                if (edge) {
+                if (edge && !(VEC4 && !F64 && 2 * 4 * g.n[1] < 0x80000000ll)) {
                     const int ex = clampi(ext[1] - 16 * lane, 0, 16);
                     store_run_masked<16, PW>(y + (yy * g.n[1] + x0), d, ebx2, step, ex);
                     if (2 * st + 1 < ext[0]) store_run_masked<16, PW>(y + ((yy + 1) * g.n[1] + x0), d + 16, ebx2, step, ex);
@@ -440,7 +488,9 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                             tile_val<PW, T>(q[2], ebx2, step), tile_val<PW, T>(q[3], ebx2, step));
                         }
                     // row offsets stay below 2^32: the contiguous extent is below 2^25
-                    store_tile_runs(tile, y + (yy * g.n[1] + org[1]), 4u * (uint32_t)g.n[1], lane);
+                    if (!edge) store_tile_runs(tile, y + (yy * g.n[1] + org[1]), 4u * (uint32_t)g.n[1], lane);
+                    else store_tile_runs_edge(tile, y + (yy * g.n[1] + org[1]), (uint32_t)g.n[1],
+                                              (uint32_t)min((int64_t)2, ext[0] - 2 * st), (uint32_t)ext[1], lane);
                 } else if constexpr (VEC4 && F64) {
                     double* t64 = reinterpret_cast<double*>(tile);
 #pragma unroll
@@ -501,16 +551,17 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 // Decompress chunk c with the stream's quantizer (the mode byte is uniform:
 // one of the two bodies runs).
 template <int RANK, bool VEC4, typename T>
-__device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, T* __restrict__ y,
-                                                     const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
+__device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, uint64_t s_bytes,
+                                                     T* __restrict__ y, const Geom& g, uint32_t* d_err, int64_t c,
+                                                     int lane, float* tile)
 {
     if constexpr (sizeof(T) == 8 || std::is_integral_v<T>) {
         // fp64 (grid modes only), or the integers of a field-global stream
         // (dequantized after the carries, in any mode)
-        decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);
+        decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
     } else {
-        if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true, T>(s, y, g, d_err, c, lane, tile);
-        else decompress_chunk<RANK, VEC4, false, T>(s, y, g, d_err, c, lane, tile);
+        if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true, T>(s, s_bytes, y, g, d_err, c, lane, tile);
+        else decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
     }
 }
 

@@ -217,11 +217,11 @@ hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mo
 
 // ------------------------------------------------------------ decompression
 template <int RANK, bool VEC4>
-__global__ __launch_bounds__(64) void k_decompress64(const uint8_t* __restrict__ s, double* __restrict__ y, Geom g,
-                                                     uint32_t* d_err)
+__global__ __launch_bounds__(64) void k_decompress64(const uint8_t* __restrict__ s, uint64_t sb, double* __restrict__ y,
+                                                     Geom g, uint32_t* d_err)
 {
     __shared__ __attribute__((aligned(16))) float tile[kTileFloats64];
-    decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
+    decompress_chunk_any<RANK, VEC4>(s, sb, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
 __global__ void k_clear_err(uint32_t* p)
@@ -230,13 +230,14 @@ __global__ void k_clear_err(uint32_t* p)
 }
 
 template <int RANK, bool VEC4>
-static hipError_t launch_rank64(const uint8_t* s, double* y, const Geom& g, uint32_t* d_err, hipStream_t st)
+static hipError_t launch_rank64(const uint8_t* s, uint64_t sb, double* y, const Geom& g, uint32_t* d_err, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_decompress64<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, y, g, d_err);
+    hipLaunchKernelGGL((k_decompress64<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, sb, y, g, d_err);
     return hipGetLastError();
 }
 
-hipError_t launch_decompress_f64(const uint8_t* s, double* y, const Geom& g, uint32_t* d_err, hipStream_t st)
+hipError_t launch_decompress_f64(const uint8_t* s, uint64_t sb, double* y, const Geom& g, uint32_t* d_err,
+                                 hipStream_t st)
 {
     if (d_err) {
         hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, st, d_err);
@@ -245,12 +246,12 @@ hipError_t launch_decompress_f64(const uint8_t* s, double* y, const Geom& g, uin
     }
     const bool vec4 = (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank64<3, true>(s, y, g, d_err, st);
-        case 6: return launch_rank64<3, false>(s, y, g, d_err, st);
-        case 5: return launch_rank64<2, true>(s, y, g, d_err, st);
-        case 4: return launch_rank64<2, false>(s, y, g, d_err, st);
-        case 3: return launch_rank64<1, true>(s, y, g, d_err, st);
-        default: return launch_rank64<1, false>(s, y, g, d_err, st);
+        case 7: return launch_rank64<3, true>(s, sb, y, g, d_err, st);
+        case 6: return launch_rank64<3, false>(s, sb, y, g, d_err, st);
+        case 5: return launch_rank64<2, true>(s, sb, y, g, d_err, st);
+        case 4: return launch_rank64<2, false>(s, sb, y, g, d_err, st);
+        case 3: return launch_rank64<1, true>(s, sb, y, g, d_err, st);
+        default: return launch_rank64<1, false>(s, sb, y, g, d_err, st);
     }
 }
 

@@ -36,8 +36,9 @@ constexpr int kLayers = 4;
 constexpr int kPlanes = 16;
 constexpr int kChunkCodes = kSteps * kStepCodes;
 constexpr int kFlagBytesPerChunk = kLayers * kPlanes * 8;
-constexpr int kLayerOutlierCap = 256;
-constexpr int kChunkOutlierCap = kLayers * kLayerOutlierCap;
+// escapes a chunk may store: 1/32 of its codes (the worst-case payload of a
+// chunk, which sizes the bound, counts this many pairs)
+constexpr int kChunkOutlierCap = 1024;
 constexpr uint32_t kEscape = 0x8000u;
 // worst-case payload of one chunk: every brick nonzero plus the escape cap
 constexpr int64_t kChunkPayloadBound = (int64_t)kLayers * kPlanes * kPatches * 16 + kChunkOutlierCap * 8;
@@ -91,6 +92,9 @@ struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into
 // per-block partials of the fp64 range pass: min and max (2 doubles), then a
 // u32 non-finite flag per block after all the doubles
 constexpr int64_t kPart64Bytes = 20 * kMinmaxBlocks;
+
+// whether p is a multiple of a (a power of two); null counts as aligned
+inline bool aligned_to(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
 {

@@ -147,11 +147,11 @@ hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t 
 
 // ------------------------------------------------------------ decompression
 template <int RANK, bool VEC4>
-__global__ __launch_bounds__(64) void k_decompress_int(const uint8_t* __restrict__ s, int32_t* __restrict__ y, Geom g,
-                                                       uint32_t* d_err)
+__global__ __launch_bounds__(64) void k_decompress_int(const uint8_t* __restrict__ s, uint64_t sb,
+                                                       int32_t* __restrict__ y, Geom g, uint32_t* d_err)
 {
     __shared__ float tile[kTileFloats];
-    decompress_chunk_any<RANK, VEC4>(s, y, g, d_err, blockIdx.x, threadIdx.x, tile);
+    decompress_chunk_any<RANK, VEC4>(s, sb, y, g, d_err, blockIdx.x, threadIdx.x, tile);
 }
 
 // Carries of the field-global prefix sums.  Along axis ax the field splits
@@ -270,9 +270,10 @@ __global__ void k_clear_err_g(uint32_t* p)
 }
 
 template <int RANK, bool VEC4>
-static hipError_t launch_rank_int(const uint8_t* s, int32_t* y, const Geom& g, uint32_t* d_err, hipStream_t st)
+static hipError_t launch_rank_int(const uint8_t* s, uint64_t sb, int32_t* y, const Geom& g, uint32_t* d_err,
+                                  hipStream_t st)
 {
-    hipLaunchKernelGGL((k_decompress_int<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, y, g, d_err);
+    hipLaunchKernelGGL((k_decompress_int<RANK, VEC4>), dim3((unsigned)g.n_chunks), dim3(64), 0, st, s, sb, y, g, d_err);
     return hipGetLastError();
 }
 
@@ -284,7 +285,7 @@ size_t global_work_bytes(const Geom& g)
     return (size_t)(4 * total);
 }
 
-hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, void* work,
+hipError_t launch_decompress_global(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err, void* work,
                                     hipStream_t st)
 {
     hipError_t e;
@@ -295,12 +296,12 @@ hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, u
     int32_t* yi = reinterpret_cast<int32_t*>(y);
     const bool vec4 = (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: e = launch_rank_int<3, true>(s, yi, g, d_err, st); break;
-        case 6: e = launch_rank_int<3, false>(s, yi, g, d_err, st); break;
-        case 5: e = launch_rank_int<2, true>(s, yi, g, d_err, st); break;
-        case 4: e = launch_rank_int<2, false>(s, yi, g, d_err, st); break;
-        case 3: e = launch_rank_int<1, true>(s, yi, g, d_err, st); break;
-        default: e = launch_rank_int<1, false>(s, yi, g, d_err, st); break;
+        case 7: e = launch_rank_int<3, true>(s, sb, yi, g, d_err, st); break;
+        case 6: e = launch_rank_int<3, false>(s, sb, yi, g, d_err, st); break;
+        case 5: e = launch_rank_int<2, true>(s, sb, yi, g, d_err, st); break;
+        case 4: e = launch_rank_int<2, false>(s, sb, yi, g, d_err, st); break;
+        case 3: e = launch_rank_int<1, true>(s, sb, yi, g, d_err, st); break;
+        default: e = launch_rank_int<1, false>(s, sb, yi, g, d_err, st); break;
     }
     if (e != hipSuccess) return e;
     uint32_t* f = reinterpret_cast<uint32_t*>(y);

@@ -10,17 +10,25 @@ struct HeaderImage {
     uint32_t w[kHeaderBytes / 4];
 };
 
+// events recorded between the launches of one compression (each may be null)
+struct Timing {
+    hipEvent_t range_begin, main_begin, main_end, done;
+};
+
 // mode: FZ_EB_ABS, FZ_EB_REL (adds the range pass) or FZ_EB_PWREL
 hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
-                           hipStream_t st);
-hipError_t launch_decompress(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);
+                           hipStream_t st, const Timing* t = nullptr);
+// decompression: sb = the bytes readable at s (at least g.payload_off,
+// checked by the caller); no byte past them is read
+hipError_t launch_decompress(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);
 // fp64 input (FZ_EB_ABS or FZ_EB_REL): the range pass (REL) and the
 // prequantization into the integer buffer at g.q_off, then the compression
 // kernel on those integers
 hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
                                double eb, hipStream_t st);
 hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mode, double eb, hipStream_t st);
-hipError_t launch_decompress_f64(const uint8_t* s, double* y, const Geom& g, uint32_t* d_err, hipStream_t st);
+hipError_t launch_decompress_f64(const uint8_t* s, uint64_t sb, double* y, const Geom& g, uint32_t* d_err,
+                                 hipStream_t st);
 // copy the header's status to the scratch's pre_status (after a pass that
 // wrote the integer buffer)
 hipError_t launch_pre_status(uint8_t* out, const Geom& g, hipStream_t st);
@@ -30,8 +38,8 @@ hipError_t launch_pre_status(uint8_t* out, const Geom& g, hipStream_t st);
 hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
                                   double eb, hipStream_t st);
 hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t st);
-hipError_t launch_decompress_global(const uint8_t* s, float* y, const Geom& g, uint32_t* d_err, void* work,
-                                    hipStream_t st);
+hipError_t launch_decompress_global(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err,
+                                    void* work, hipStream_t st);
 size_t global_work_bytes(const Geom& g);
 
 // blocks of the REL range pass of a field of n values

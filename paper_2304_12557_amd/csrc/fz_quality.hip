@@ -192,6 +192,7 @@ int fz_quality(const float* d_x, const float* d_y, const fz_dims* dims, fz_quali
 {
     Geom g;
     if (!d_x || !d_y || !d_res || !d_work || !dims || !make_geom((int)dims->rank, dims->n, &g)) return FZ_ERR_ARG;
+    if (!aligned_to(d_x, 4) || !aligned_to(d_y, 4) || !aligned_to(d_res, 8) || !aligned_to(d_work, 256)) return FZ_ERR_ARG;
     const int64_t n = g.n[0] * g.n[1] * g.n[2];
     const int64_t blocks = qual_blocks(n);
     hipStream_t st = static_cast<hipStream_t>(stream);

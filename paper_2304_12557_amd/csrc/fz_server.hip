@@ -115,8 +115,15 @@ int launch(fz_server* S, Slot& sl, const std::vector<uint64_t>& tickets)
             j.dims = r.dims;
             j.d_out = static_cast<float*>(r.d_out);
             j.d_err = r.d_err;
+            j.stream_bytes = r.stream_bytes;
             dj.push_back(j);
         }
+    }
+    // the caller's work that produces the inputs (and last uses the outputs)
+    for (uint64_t t : tickets) {
+        const fz_request& r = S->reqs[t].r;
+        if (r.ready_event && hipStreamWaitEvent(sl.stream, static_cast<hipEvent_t>(r.ready_event), 0) != hipSuccess)
+            return FZ_ERR_HIP;
     }
     uint8_t* dev = static_cast<uint8_t*>(sl.dev);
     uint8_t* pin = static_cast<uint8_t*>(sl.pinned);
@@ -138,7 +145,8 @@ int launch(fz_server* S, Slot& sl, const std::vector<uint64_t>& tickets)
         } else {  // too many chunks for the slot's tables: per-field launches
             for (int i = 0; i < n; i++) {
                 rc = kind == 0 ? fz_compress(cj[i].d_in, &cj[i].dims, cj[i].eb, cj[i].eb_mode, cj[i].d_out, sl.stream)
-                               : fz_decompress(dj[i].d_stream, dj[i].d_out, &dj[i].dims, dj[i].d_err, sl.stream);
+                               : fz_decompress(dj[i].d_stream, dj[i].stream_bytes, dj[i].d_out, &dj[i].dims,
+                                               dj[i].d_err, sl.stream);
                 if (rc != FZ_OK) return rc;
             }
         }
@@ -285,11 +293,15 @@ int fz_server_submit(fz_server* S, const fz_request* r, uint64_t* ticket)
     if (r->kind == FZ_REQ_COMPRESS) {
         if (!(r->eb > 0.0) || !std::isfinite(r->eb) || (r->eb_mode != FZ_EB_ABS && r->eb_mode != FZ_EB_REL))
             return FZ_ERR_ARG;
+        if (!aligned_to(r->d_in, 4) || !aligned_to(r->d_out, 256)) return FZ_ERR_ARG;
         float e2, iv;
         if (r->eb_mode == FZ_EB_ABS && !abs_params(r->eb, &e2, &iv)) return FZ_ERR_EB_RANGE;
         if (!bytes) bytes = 4 * n + (uint64_t)g.bound;
     } else if (r->kind == FZ_REQ_DECOMPRESS) {
-        if (!bytes) bytes = 4 * n + (uint64_t)g.bound;
+        if (!aligned_to(r->d_in, 256) || !aligned_to(r->d_out, 4) || !aligned_to(r->d_err, 4) ||
+            r->stream_bytes < (uint64_t)g.payload_off)
+            return FZ_ERR_ARG;
+        if (!bytes) bytes = 4 * n + r->stream_bytes;
     } else {
         return FZ_ERR_ARG;
     }

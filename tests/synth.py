@@ -195,7 +195,7 @@ def wide_field(shape, seed):
     sign = np.where(sine_field(shape, seed=seed + 1) > 3.5, -1.0, 1.0)
     x = (mag * sign).astype(np.float32)
     flat = x.reshape(-1)
-    # each special value costs up to 8 escaped deltas; a layer holds at most 256
+    # each special value costs up to 8 escaped deltas; a chunk holds at most 1024
     flat[::1009] = 0.0
     flat[7::2111] = np.float32(3e-42)
     flat[5::3001] = rng.standard_normal(flat[5::3001].size).astype(np.float32) * np.float32(1e30)

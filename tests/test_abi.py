@@ -38,36 +38,81 @@ def test_sizes_match_oracle(shape):
     assert fz.compress_bound(shape) >= O.bound(shape)
 
 
+# a 256-byte aligned stand-in pointer: every call below fails an argument
+# check before anything is enqueued, so it is never dereferenced
+P = ctypes.c_void_p(4096)
+
+
 def test_argument_errors_return_immediately():
     L = fz.lib()
     d = fz.dims_of((10, 10))
-    assert L.fz_compress(None, ctypes.byref(d), 1e-3, 1, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), -1.0, 1, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), float("nan"), 1, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 7, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-45, 0, ctypes.c_void_p(16), None) == 4
+    assert L.fz_compress(None, ctypes.byref(d), 1e-3, 1, P, None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), -1.0, 1, P, None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), float("nan"), 1, P, None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), 1e-3, 7, P, None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), 1e-45, 0, P, None) == 4
     # point-wise relative mode: a step S = floor(eps 2^24 / (1 + eps)) below 2 is out of range
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-8, 2, ctypes.c_void_p(16), None) == 4
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1.1e-7, 2, ctypes.c_void_p(16), None) == 4
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 3, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), 1e-8, 2, P, None) == 4
+    assert L.fz_compress(P, ctypes.byref(d), 1.1e-7, 2, P, None) == 4
+    assert L.fz_compress(P, ctypes.byref(d), 1e-3, 3, P, None) == 1
     # fp64 input: grid modes only; 2 eb below the smallest normal double is out of range
-    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 2, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress_f64(None, ctypes.byref(d), 1e-3, 0, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), float("inf"), 0, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress_f64(ctypes.c_void_p(16), ctypes.byref(d), 1e-310, 0, ctypes.c_void_p(16), None) == 4
-    assert L.fz_decompress_f64(None, ctypes.c_void_p(16), ctypes.byref(d), None, None) == 1
+    assert L.fz_compress_f64(P, ctypes.byref(d), 1e-3, 2, P, None) == 1
+    assert L.fz_compress_f64(None, ctypes.byref(d), 1e-3, 0, P, None) == 1
+    assert L.fz_compress_f64(P, ctypes.byref(d), float("inf"), 0, P, None) == 1
+    assert L.fz_compress_f64(P, ctypes.byref(d), 1e-310, 0, P, None) == 4
+    assert L.fz_decompress_f64(None, 1 << 20, P, ctypes.byref(d), None, None) == 1
     # field-global predictor: the chunk-local checks, and a work buffer is required
-    assert L.fz_compress_global(ctypes.c_void_p(16), ctypes.byref(d), -1.0, 1, ctypes.c_void_p(16), None) == 1
-    assert L.fz_compress_global(ctypes.c_void_p(16), ctypes.byref(d), 1e-8, 2, ctypes.c_void_p(16), None) == 4
-    assert L.fz_decompress_global(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.byref(d), None, None, None) == 1
+    assert L.fz_compress_global(P, ctypes.byref(d), -1.0, 1, P, None) == 1
+    assert L.fz_compress_global(P, ctypes.byref(d), 1e-8, 2, P, None) == 4
+    assert L.fz_decompress_global(P, 1 << 20, P, ctypes.byref(d), None, None, None) == 1
     bad = fz.FzDims()
     bad.rank = 4
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(bad), 1e-3, 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(P, ctypes.byref(bad), 1e-3, 1, P, None) == 1
     bad.rank = 2
     bad.n[0], bad.n[1] = 0, 5
     assert L.fz_compress_bound(ctypes.byref(bad)) == 0
-    assert L.fz_decompress(None, ctypes.c_void_p(16), ctypes.byref(d), None, None) == 1
+    assert L.fz_decompress(None, 1 << 20, P, ctypes.byref(d), None, None) == 1
     assert fz.lib().fz_strerror(6) == b"malformed stream"
+
+
+def test_misaligned_and_short_buffers_are_argument_errors():
+    """Buffers the kernels address with atomics and 8/16-byte accesses must
+    be aligned (256 bytes for whole buffers, 4 for the error word, 8 for the
+    quality report), and a decompression's stream_bytes must cover at least
+    the header, table and flags: otherwise FZ_ERR_ARG before any launch."""
+    L = fz.lib()
+    d = fz.dims_of((10, 10))
+    hb = fz.header_bytes((10, 10))
+    off = ctypes.c_void_p(4096 + 16)
+    for fn in (L.fz_compress, L.fz_compress_global, L.fz_compress_f64):
+        assert fn(P, ctypes.byref(d), 1e-3, 1, off, None) == 1  # output not on 256 bytes
+    assert L.fz_compress(ctypes.c_void_p(4098), ctypes.byref(d), 1e-3, 1, P, None) == 1  # input not on 4
+    assert L.fz_compress_f64(ctypes.c_void_p(4100), ctypes.byref(d), 1e-3, 1, P, None) == 1  # fp64 input not on 8
+    for fn in (L.fz_decompress, L.fz_decompress_f64):
+        assert fn(off, 1 << 20, P, ctypes.byref(d), None, None) == 1          # stream not on 256
+        assert fn(P, 1 << 20, P, ctypes.byref(d), ctypes.c_void_p(4098), None) == 1  # error word not on 4
+        assert fn(P, hb - 1, P, ctypes.byref(d), None, None) == 1             # stream shorter than its header
+    assert L.fz_decompress(P, 1 << 20, ctypes.c_void_p(4098), ctypes.byref(d), None, None) == 1
+    assert L.fz_decompress_f64(P, 1 << 20, ctypes.c_void_p(4100), ctypes.byref(d), None, None) == 1
+    assert L.fz_decompress_global(P, 1 << 20, P, ctypes.byref(d), None, off, None) == 1  # work not on 256
+    assert L.fz_decompress_global(P, hb - 1, P, ctypes.byref(d), None, P, None) == 1
+    assert L.fz_quality(P, P, ctypes.byref(d), ctypes.c_void_p(4100), P, None) == 1  # report not on 8
+    assert L.fz_quality(P, P, ctypes.byref(d), P, off, None) == 1                    # work not on 256
+    # batch jobs and server requests make the same checks
+    jobs = (fz.FzCompressJob * 1)()
+    jobs[0].d_in, jobs[0].d_out, jobs[0].eb, jobs[0].eb_mode = 4096, 4096 + 16, 1e-3, fz.FZ_EB_REL
+    jobs[0].dims = d
+    h = ctypes.c_void_p(123)
+    assert L.fz_batch_create_compress(1, jobs, ctypes.byref(h)) == 1 and not h.value
+    djobs = (fz.FzDecompressJob * 1)()
+    djobs[0].d_stream, djobs[0].d_out, djobs[0].dims, djobs[0].stream_bytes = 4096, 4096, d, hb - 1
+    assert L.fz_batch_create_decompress(1, djobs, ctypes.byref(h)) == 1
+    djobs[0].stream_bytes, djobs[0].d_stream = 1 << 20, 4096 + 64
+    assert L.fz_batch_create_decompress(1, djobs, ctypes.byref(h)) == 1
+    # the binding refuses the same before calling in
+    import torch
+    with pytest.raises(ValueError):
+        fz._check_buffer(torch.zeros(4), "t", (torch.float32,), 4)  # a host tensor
 
 
 def test_stream_info_parses_oracle_header():
@@ -97,7 +142,7 @@ def test_size_limits():
     assert bound(2, (4, (1 << 25) - 1))[0] > 0
     b, d = bound(2, (4, 1 << 25))
     assert b == 0
-    assert L.fz_compress(ctypes.c_void_p(16), ctypes.byref(d), 1e-3, 1, ctypes.c_void_p(16), None) == 1
+    assert L.fz_compress(P, ctypes.byref(d), 1e-3, 1, P, None) == 1
     assert bound(3, (2, 3, 1 << 25))[0] == 0
     assert bound(1, (1 << 40,))[0] > 0
     assert bound(1, ((1 << 40) + 1,))[0] == 0
@@ -112,7 +157,7 @@ def test_batch_create_rejects_bad_jobs():
     L = fz.lib()
     jobs = (fz.FzCompressJob * 2)()
     for j in jobs:
-        j.d_in, j.d_out, j.eb, j.eb_mode = 16, 16, 1e-3, fz.FZ_EB_REL
+        j.d_in, j.d_out, j.eb, j.eb_mode = 4096, 4096, 1e-3, fz.FZ_EB_REL
         j.dims = fz.dims_of((10, 10))
     jobs[1].eb = -1.0
     h = ctypes.c_void_p(123)
@@ -122,7 +167,7 @@ def test_batch_create_rejects_bad_jobs():
     assert L.fz_batch_create_compress(2, jobs, ctypes.byref(h)) == 4
     assert L.fz_batch_create_compress(0, jobs, ctypes.byref(h)) == 1
     djobs = (fz.FzDecompressJob * 1)()
-    djobs[0].d_stream, djobs[0].d_out, djobs[0].dims = None, 16, fz.dims_of((5,))
+    djobs[0].d_stream, djobs[0].d_out, djobs[0].dims = None, 4096, fz.dims_of((5,))
     assert L.fz_batch_create_decompress(1, djobs, ctypes.byref(h)) == 1
     assert L.fz_batch_run(None, None) == 1
     assert L.fz_batch_destroy(None) == 1
@@ -136,7 +181,8 @@ def test_server_argument_errors():
     assert L.fz_server_create(1 << 30, 0, 8, ctypes.byref(h)) == 1
     assert L.fz_server_create(1 << 30, 2, 0, ctypes.byref(h)) == 1
     t = ctypes.c_uint64()
-    r = fz.FzRequest(kind=0, eb_mode=1, eb=1e-3, dims=fz.dims_of((10,)), d_in=16, d_out=16, d_err=None, hbm_bytes=0)
+    r = fz.FzRequest(kind=0, eb_mode=1, eb=1e-3, dims=fz.dims_of((10,)), d_in=4096, d_out=4096, d_err=None,
+                     hbm_bytes=0, stream_bytes=0, ready_event=None)
     assert L.fz_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == 1
     assert L.fz_server_wait(None, 1, None) == 1
     assert L.fz_server_destroy(None) == 1

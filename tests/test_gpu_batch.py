@@ -2,9 +2,10 @@
 
 * Every field of a mixed batch (ranks 1-3, aligned and unaligned rows, REL
   and ABS bounds, sizes from one chunk to several hundred) gets exactly the
-  bytes of the per-field call, and a few of them are also checked against
-  the oracle; the batched decompression gives the per-field reconstruction
-  bit for bit.
+  oracle's bytes and the per-field call's; the batched decompression gives
+  the oracle's reconstruction and the per-field call's, bit for bit.
+* The benchmark's batch (256 fields of 16 KiB - 64 MiB, 2.6 GB) against the
+  oracle, field by field, in both directions.
 * A field whose REL pass fails (NaN) gets the per-field status; its
   neighbours in the batch are unaffected.
 * A run captured in a graph and replayed several times, with eager work in
@@ -65,9 +66,9 @@ def test_batch_compress_equals_plain_calls(batch):
     got = batch_streams(b.run())
     for i, (r, s) in enumerate(zip(ref, got)):
         assert r.size == s.size and np.array_equal(r, s), (i, fields[i].shape)
-    for i in (0, len(fields) - 4, len(fields) - 1):  # and the oracle, on a few
+    for i in range(len(fields)):  # and the oracle, on every field
         o, st = O.compress(fields[i], ebs[i], O.EB_REL if modes[i] == "rel" else O.EB_ABS)
-        assert np.array_equal(o, got[i]), i
+        assert st == 0 and np.array_equal(o, got[i]), i
     b.close()
 
 
@@ -82,7 +83,49 @@ def test_batch_decompress_equals_plain_calls(batch):
     for i, (r, y, e) in enumerate(zip(ref, ys, errs)):
         assert int(e.item()) == 0
         assert torch.equal(r.view(torch.int32), y.view(torch.int32)), i
+    # and the oracle's reconstruction of the oracle's stream, on every field
+    for i, f in enumerate(fields):
+        o, st = O.compress(f, ebs[i], O.EB_REL if modes[i] == "rel" else O.EB_ABS)
+        yo, err = O.decompress(o, f.shape)
+        assert st == 0 and err == 0
+        assert np.array_equal(ys[i].cpu().numpy().view(np.uint32), yo.view(np.uint32)), i
     b.close()
+
+
+def test_batch_benchmark_scale_against_oracle():
+    """The benchmark's batch: 256 fields of rank 1-3 with log-uniform sizes
+    of 16 KiB - 64 MiB (2.6 GB in all), sine workload generated on the device
+    and copied to the host for the oracle, REL bounds from {1e-2, 1e-3, 1e-4}.
+    One batched compression and one batched decompression, every field
+    against the oracle (threaded compression, single-threaded decompression)."""
+    import os
+
+    threads = min(os.cpu_count() or 1, 16)
+    dev = torch.device("cuda")
+    shapes = synth.batch_shapes(n_fields=256, seed=3000)
+    xs = [synth.sine_field_device(sh, 3000 + i, dev) for i, sh in enumerate(shapes)]
+    ebs = [synth.rel_eb_choice(3000 + i) for i in range(len(shapes))]
+    print("benchmark batch: %d fields, %.2f GB" % (len(xs), sum(4 * x.numel() for x in xs) / 1e9), flush=True)
+    b = fz.Batch.compress([(x, eb, "rel", None) for x, eb in zip(xs, ebs)])
+    outs = b.run()
+    torch.cuda.synchronize()
+    streams = [o[:fz.stream_size(o)].clone() for o in outs]
+    b.close()
+    del outs
+    errs = [torch.ones(1, dtype=torch.int32, device=dev) for _ in xs]
+    d = fz.Batch.decompress([(s, x.shape, None, e) for s, x, e in zip(streams, xs, errs)])
+    ys = d.run()
+    torch.cuda.synchronize()
+    for i, (x, eb) in enumerate(zip(xs, ebs)):
+        xh = x.cpu().numpy()
+        o, st = O.compress(xh, eb, O.EB_REL, threads=threads)
+        assert st == 0
+        s = streams[i].cpu().numpy()
+        assert s.size == o.size and np.array_equal(s, o), (i, shapes[i])
+        assert int(errs[i].item()) == 0, i
+        yo, err = O.decompress(o, xh.shape)
+        assert err == 0 and np.array_equal(ys[i].cpu().numpy().view(np.uint32), yo.view(np.uint32)), (i, shapes[i])
+    d.close()
 
 
 def test_batch_failing_field_is_isolated():

@@ -4,19 +4,17 @@ benchmark times (the library chooses it from the field's shape).
 * 2-D climate-like 1800x3600 (REL 1e-4) and 3-D hurricane-like 100x500x500
   (REL 1e-3, 1e-4): the whole stream byte for byte and the whole
   reconstruction bit for bit against the oracle.
-* 3-D cosmology-like 512^3 (REL 1e-2, 1e-3, 1e-4), where the oracle's full run
-  would dominate the test time:
-  - the eb parameters against the oracle's own computation on the field;
+* 3-D cosmology-like 512^3 (REL 1e-2, 1e-3, 1e-4, and ABS with the absolute
+  bound REL 1e-3 produces, the benchmark's second mode): the whole stream
+  byte for byte and the whole reconstruction bit for bit against the oracle
+  (threaded compression, about 0.6 s each; single-threaded decompression,
+  about 1.1 s), plus properties that hold without it:
   - every reconstructed value against its closed form
     fp32((float)rint(fp32(x*inv)) * ebx2) (the stages after prequantization
     are lossless, Sec. 2.3 / 3.2-3.4), computed here in numpy;
   - the size identities of the zero-block encoder (Sec. 3.4): total bytes =
     header + 16 * (nonzero bricks + escape pairs / 2 rounded up), nonzero
-    bricks = popcount of all flags;
-  - a seeded sample of chunks (first, last and random ones) byte for byte:
-    the Lorenzo predictor is chunk-local, so the oracle compressing one
-    chunk's box alone, with the same eb parameters, must produce that chunk's
-    flags, escape count and payload.
+    bricks = popcount of all flags, the table the exclusive prefix sum.
 """
 import os
 
@@ -77,19 +75,28 @@ def _geometry(shape):
     return box, grid, nch, table_off, flags_off, payload_off
 
 
-@pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
-def test_cosmology_512(cosmo, eb):
+@pytest.mark.parametrize("mode,eb", [("rel", 1e-2), ("rel", 1e-3), ("rel", 1e-4), ("abs", None)])
+def test_cosmology_512(cosmo, mode, eb):
     x = cosmo
-    print("case lognormal 512^3", eb, flush=True)
-    s, y = run_gpu(x, eb)
+    if mode == "abs":  # the absolute bound REL 1e-3 gives this field
+        p = O.eb_params(x, 1e-3, O.EB_REL)
+        eb = 1e-3 * (float(p["vmax"]) - float(p["vmin"]))
+    print("case lognormal 512^3", mode, eb, flush=True)
+    s, y = run_gpu(x, eb, mode)
     h = stream_np.header(s)
     assert h["status"] == 0
 
-    # eb parameters (Sec. 4.1): the oracle's computation on the whole field
-    p = O.eb_params(x, eb, O.EB_REL)
-    assert p["status"] == 0
-    for k in ("ebx2", "inv", "vmin", "vmax"):
-        assert np.float32(h[k]).view(np.uint32) == np.float32(p[k]).view(np.uint32), k
+    # the whole stream and reconstruction against the oracle
+    ref, st = O.compress(x, eb, O.EB_REL if mode == "rel" else O.EB_ABS, threads=THREADS)
+    assert st == 0
+    assert s.size == ref.size, (s.size, ref.size)
+    if not np.array_equal(s, ref):
+        diff = np.nonzero(s != ref)[0]
+        raise AssertionError("stream differs at %d bytes, first at %d of %d" % (diff.size, diff[0], s.size))
+    yo, err = O.decompress(ref, x.shape)
+    assert err == 0
+    assert np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+    del ref, yo
 
     # every value: the closed form of prequantization + dequantization
     inv, ebx2 = np.float32(h["inv"]), np.float32(h["ebx2"])
@@ -110,26 +117,6 @@ def test_cosmology_512(cosmo, eb):
     units = np.unpackbits(per_chunk_flags.view(np.uint8), axis=1).sum(axis=1).astype(np.int64) + (table[:, 1] + 1) // 2
     assert h["total"] == payload_off + 16 * int(units.sum())
     assert np.array_equal(table[:, 0].astype(np.int64), np.concatenate([[0], np.cumsum(units)[:-1]]))
-
-    # sampled chunks against the oracle on the chunk's box alone (ABS mode with
-    # the same eb_abs, hence the same ebx2 and inv)
-    eb_abs = eb * (float(h["vmax"]) - float(h["vmin"]))
-    rng = np.random.default_rng(12345)
-    sample = sorted(set([0, nch - 1, nch // 2] + list(rng.choice(nch, 21, replace=False))))
-    for c in sample:
-        cz, cy, cx = c // (grid[1] * grid[2]), (c // grid[2]) % grid[1], c % grid[2]
-        sub = np.ascontiguousarray(x[cz * box[0]:(cz + 1) * box[0], cy * box[1]:(cy + 1) * box[1],
-                                     cx * box[2]:(cx + 1) * box[2]])
-        ref, st = O.compress(sub, eb_abs, O.EB_ABS)
-        assert st == 0
-        hr = stream_np.header(ref)
-        assert np.float32(hr["ebx2"]) == ebx2 and np.float32(hr["inv"]) == inv
-        # one-chunk stream: header 128, table 16, flags 512, then the payload
-        assert np.array_equal(ref[144:656], s[flags_off + 512 * c:flags_off + 512 * (c + 1)]), c
-        rtab = ref[128:136].view(np.uint32)
-        assert rtab[1] == table[c, 1], c
-        start = payload_off + 16 * int(table[c, 0])
-        assert np.array_equal(ref[656:], s[start:start + ref.size - 656]), c
 
 
 def test_cosmology_512_quality(cosmo):

@@ -94,6 +94,36 @@ def test_parity_escapes():
     check_case(x1, 1e-3, O.EB_ABS)
 
 
+@pytest.mark.parametrize("shape,count,rows", [
+    ((32768,), 150, (0, 8190)),            # 300 escapes in layer 0 of a 1-D chunk
+    ((32768,), 129, (8192, 16382)),        # 258 in layer 1
+    ((32768,), 512, (16384, 24574)),       # the chunk's whole allowance (1024) in layer 2
+    ((16, 32, 64), 40, (4, 7)),            # 3-D, 320 in layer 1 (swept downwards on the fast path)
+    ((16, 32, 64), 128, (12, 15)),         # 3-D, 1024 in layer 3
+    ((32, 1024), 100, (8, 15)),            # 2-D, 400 in layer 1
+    ((33, 70, 130), 300, (4, 7)),          # 3-D, several chunks, edge chunks among them
+    ((70, 2100), 400, (40, 47)),           # 2-D, several chunks
+])
+def test_parity_escapes_crowded_in_one_layer(shape, count, rows):
+    """A chunk may hold up to 1024 escapes wherever they fall: layers with
+    more than 256 (and up to all 1024) give the oracle's stream."""
+    x = synth.spike_field(shape, count, rows, seed=17)
+    s = check_case(x, 0.5, O.EB_ABS)
+    info = fz.stream_info(s[:128].tobytes())
+    assert info["n_outliers"] > 256 and info["status"] == 0
+
+
+def test_escape_cap_per_chunk_matches_oracle():
+    x = synth.spike_field((32768,), 512, (16384, 24574), seed=18)
+    x[30000:] = np.float32(100000.0)  # 1025 escapes in one chunk: the cap
+    _, st = O.compress(x, 0.5, O.EB_ABS)
+    buf, _ = gpu_compress(x, 0.5, O.EB_ABS)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_OUTLIER_CAP
+    x2 = np.concatenate([synth.spike_field((32768,), 512, (16384, 24574), seed=18), np.zeros(32768, np.float32)])
+    x2[40000:] = np.float32(100000.0)  # 1024 + 1 over two chunks: a valid stream
+    check_case(x2, 0.5, O.EB_ABS)
+
+
 def test_status_bits_match_oracle():
     x = synth.sine_field((20, 40, 70), seed=1)
     bad = x.copy()
@@ -167,6 +197,39 @@ def test_decompress_rejects_bad_stream():
     _, err = gpu_decompress(bad, x.shape)
     assert err == 7
     _, err = gpu_decompress(buf, (20, 40, 71))
+    assert err == 6
+
+
+def test_decompress_bounds_and_table_checks():
+    """The device reads no byte past stream_bytes and checks the chunk table
+    against the flags: a stream cut short (in a buffer of exactly the cut
+    length), a total beyond the buffer, a table offset moved by one unit, and
+    a flag bit set without its brick are all rejected with FZ_ERR_STREAM;
+    the intact stream in an exact-size buffer decodes."""
+    x = synth.sine_field((40, 70, 130), seed=8)  # 24 chunks
+    buf, s = gpu_compress(x, 1e-3, O.EB_REL)
+    exact = torch.from_numpy(s.copy()).cuda()
+    y, err = gpu_decompress(exact, x.shape)
+    yo, _ = O.decompress(s, x.shape)
+    assert err == 0 and np.array_equal(y.view(np.uint32), yo.view(np.uint32))
+    hb = fz.header_bytes(x.shape)
+    for cut in (hb, hb + 16, (hb + s.size) // 2, s.size - 16):
+        short = torch.from_numpy(s[:cut].copy()).cuda()
+        _, err = gpu_decompress(short, x.shape)
+        assert err == 6, cut
+    nch = fz.stream_info(s[:128].tobytes())["n_chunks"]
+    for c in (1, nch // 2, nch - 1):  # chunk c's offset, one unit later
+        t = s.copy()
+        tab = t[128:128 + 8 * nch].view(np.uint32).reshape(nch, 2)
+        tab[c, 0] += 1
+        _, err = gpu_decompress(torch.from_numpy(t).cuda(), x.shape)
+        assert err == 6, c
+    t = s.copy()
+    flags = t[hb - 512 * nch:hb].view(np.uint64)
+    zero = np.nonzero(flags[:64] != np.uint64(0xFFFFFFFFFFFFFFFF))[0][0]  # a flag word of chunk 0 with a free bit
+    free = [b for b in range(64) if not (int(flags[zero]) >> b) & 1][0]
+    flags[zero] |= np.uint64(1) << np.uint64(free)
+    _, err = gpu_decompress(torch.from_numpy(t).cuda(), x.shape)
     assert err == 6
 
 

@@ -91,12 +91,12 @@ def test_zeros_signed_zeros_and_denormals():
 
 
 def test_statuses():
-    # this field's sign regions escape more than the cap allows in one layer;
-    # a non-finite value ends the pipeline first, so only its bit is set
+    # this field's sign regions put 287 escapes in one layer (859 in its
+    # chunk, within the chunk's allowance of 1024): a valid stream
     x = synth.wide_field((20, 40, 70), seed=8)
-    _, st = O.compress(x, 1e-3, O.EB_PWREL)
-    gst, _, _, _ = gpu_run(x, 1e-3)
-    assert gst == st == O.ERR_OUTLIER_CAP
+    s = check(x, 1e-3)
+    assert fz.stream_info(torch.from_numpy(s).cuda())["n_outliers"] > 1024
+    # a non-finite value ends the pipeline first, so only its bit is set
     for v in (np.nan, np.inf, -np.inf):
         bad = x.copy()
         bad[7, 11, 13] = v
