@@ -656,10 +656,16 @@ def bench_ablation(xt, inv, t_fused_ms, reps=10):
     r["mark_us"] = timed(ab.mark)
     r["bitshuffle_mark_v1_us"] = r["bitshuffle_us"] + r["mark_us"]
     r["bitshuffle_mark_v2_us"] = timed(ab.bitshuffle_mark)
+    # the same two variants with the transpose done by wave votes (Sec. 3.3)
+    r["bitshuffle_ballot_us"] = timed(lambda: ab.bitshuffle(ballot=True))
+    r["bitshuffle_mark_v1_ballot_us"] = r["bitshuffle_ballot_us"] + r["mark_us"]
+    r["bitshuffle_mark_v2_ballot_us"] = timed(lambda: ab.bitshuffle_mark(ballot=True))
     out = {k: (round(v, 1) if k.endswith("_us") else v) for k, v in r.items()}
     out["speedup_pred_quant"] = round(r["pred_quant_v1_us"] / r["pred_quant_v2_us"], 3)
     out["speedup_bitshuffle_mark"] = round(r["bitshuffle_mark_v1_us"] / r["bitshuffle_mark_v2_us"], 3)
     out["speedup_encode"] = round(r["encode_v1_us"] / r["encode_v2_us"], 3)
+    out["speedup_swar_over_ballot_shuffle"] = round(r["bitshuffle_ballot_us"] / r["bitshuffle_us"], 3)
+    out["speedup_swar_over_ballot_shuffle_mark"] = round(r["bitshuffle_mark_v2_ballot_us"] / r["bitshuffle_mark_v2_us"], 3)
     out["unfused_v2_pipeline_us"] = round(r["pred_quant_v2_us"] + r["bitshuffle_mark_v2_us"] + r["encode_v2_us"], 1)
     out["fused_compress_abs_us"] = round(t_fused_ms * 1e3, 1)
     del ab
@@ -852,7 +858,7 @@ def main():
         "compress_pct_hbm": round(100 * in_bytes / 1e9 / (tc * 1e-3) / HBM_PEAK_GBPS, 2),
         "compress_abs_pct_hbm": round(100 * in_bytes / 1e9 / (ab["compress"] * 1e-3) / HBM_PEAK_GBPS, 2),
         "decompress_pct_hbm": round(100 * in_bytes / 1e9 / (td * 1e-3) / HBM_PEAK_GBPS, 2),
-        "end_to_end_target": "ABS compression >= 50 % of HBM peak over the input bytes (t <= %.0f us here)"
+        "end_to_end_target": "ABS compression >= 50 %% of HBM peak over the input bytes (t <= %.0f us here)"
                              % (in_bytes / 4e12 * 1e6),
         "ratio": round(in_bytes / s_bytes, 3),
         "stream_bytes": s_bytes,

@@ -417,6 +417,17 @@ int fz_abl_mark(const uint32_t *d_tiles, const fz_dims *dims, uint64_t *d_flags,
 int fz_abl_bitshuffle_mark(const uint16_t *d_codes, const fz_dims *dims, uint32_t *d_tiles, uint64_t *d_flags,
                            void *stream);
 
+/* fz_abl_bitshuffle_ballot, fz_abl_bitshuffle_mark_ballot -- the same tiles
+ * (and flags) as fz_abl_bitshuffle and fz_abl_bitshuffle_mark, with the
+ * transpose done the way Sec. 3.3 does it: the tile's codes pass through
+ * shared memory two to a 32-bit word, and one wave vote per bit gathers that
+ * bit over the wave's words (64 lanes: one vote gives the plane word of two
+ * patches).  512 votes per step instead of the in-register transpose of the
+ * other two; the outputs are identical. */
+int fz_abl_bitshuffle_ballot(const uint16_t *d_codes, const fz_dims *dims, uint32_t *d_tiles, void *stream);
+int fz_abl_bitshuffle_mark_ballot(const uint16_t *d_codes, const fz_dims *dims, uint32_t *d_tiles,
+                                  uint64_t *d_flags, void *stream);
+
 /* fz_abl_encode -- Sec. 3.4: d_offsets (steps + 1 u64) receives the exclusive
  * prefix sum of the per-step nonzero block counts (its last entry the
  * total); d_out (N * 2 bytes) the nonzero 16-byte blocks, step by step in

@@ -153,9 +153,11 @@ def lib():
         L.fz_abl_bitshuffle.argtypes = [vp, dp, vp, vp]
         L.fz_abl_mark.argtypes = [vp, dp, vp, vp]
         L.fz_abl_bitshuffle_mark.argtypes = [vp, dp, vp, vp, vp]
+        L.fz_abl_bitshuffle_ballot.argtypes = [vp, dp, vp, vp]
+        L.fz_abl_bitshuffle_mark_ballot.argtypes = [vp, dp, vp, vp, vp]
         L.fz_abl_encode.argtypes = [vp, vp, dp, vp, vp, vp]
         for name in ("fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark",
-                     "fz_abl_encode"):
+                     "fz_abl_bitshuffle_ballot", "fz_abl_bitshuffle_mark_ballot", "fz_abl_encode"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -166,7 +168,7 @@ SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_compress_t
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
            "fz_abl_pred_quant", "fz_abl_bitshuffle", "fz_abl_mark", "fz_abl_bitshuffle_mark", "fz_abl_encode",
-           "fz_compress_bound_f64", "fz_compress_f64", "fz_decompress_f64", "fz_compress_bound_global",
+           "fz_abl_bitshuffle_ballot", "fz_abl_bitshuffle_mark_ballot", "fz_compress_bound_f64", "fz_compress_f64", "fz_decompress_f64", "fz_compress_bound_global",
            "fz_compress_global", "fz_decompress_global_work_bytes", "fz_decompress_global"]
 FZ_REQ_COMPRESS = 0
 FZ_REQ_DECOMPRESS = 1
@@ -376,20 +378,20 @@ class Ablation:
                                            ctypes.c_void_p(self.outliers.data_ptr()), _stream_ptr(stream)),
                    "fz_abl_pred_quant")
 
-    def bitshuffle(self, stream=None):
-        self._call(lib().fz_abl_bitshuffle(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
-                                           ctypes.c_void_p(self.tiles.data_ptr()), _stream_ptr(stream)),
-                   "fz_abl_bitshuffle")
+    def bitshuffle(self, stream=None, ballot=False):
+        name = "fz_abl_bitshuffle_ballot" if ballot else "fz_abl_bitshuffle"
+        self._call(getattr(lib(), name)(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
+                                        ctypes.c_void_p(self.tiles.data_ptr()), _stream_ptr(stream)), name)
 
     def mark(self, stream=None):
         self._call(lib().fz_abl_mark(ctypes.c_void_p(self.tiles.data_ptr()), ctypes.byref(self.dims),
                                      ctypes.c_void_p(self.flags.data_ptr()), _stream_ptr(stream)), "fz_abl_mark")
 
-    def bitshuffle_mark(self, stream=None):
-        self._call(lib().fz_abl_bitshuffle_mark(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
-                                                ctypes.c_void_p(self.tiles.data_ptr()),
-                                                ctypes.c_void_p(self.flags.data_ptr()), _stream_ptr(stream)),
-                   "fz_abl_bitshuffle_mark")
+    def bitshuffle_mark(self, stream=None, ballot=False):
+        name = "fz_abl_bitshuffle_mark_ballot" if ballot else "fz_abl_bitshuffle_mark"
+        self._call(getattr(lib(), name)(ctypes.c_void_p(self.codes.data_ptr()), ctypes.byref(self.dims),
+                                        ctypes.c_void_p(self.tiles.data_ptr()),
+                                        ctypes.c_void_p(self.flags.data_ptr()), _stream_ptr(stream)), name)
 
     def encode(self, stream=None):
         self._call(lib().fz_abl_encode(ctypes.c_void_p(self.tiles.data_ptr()), ctypes.c_void_p(self.flags.data_ptr()),

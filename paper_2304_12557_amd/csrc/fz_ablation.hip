@@ -169,19 +169,80 @@ __global__ __launch_bounds__(64) void k_abl_mark(const uint32_t* __restrict__ ti
     if (lane < 4) flags[(int64_t)blockIdx.x * 4 + lane] = mine;
 }
 
-// bitshuffle-mark v2: the flags come from the words in registers
-__global__ __launch_bounds__(64) void k_abl_shuffle_mark(const uint16_t* __restrict__ codes, AblGeom g,
-                                                         uint32_t* __restrict__ tiles, uint64_t* __restrict__ flags)
+// ------------------------------------------------ ballot bitshuffle (Sec. 3.3)
+// The paper's transpose: the codes of a tile sit in shared memory two to a
+// 32-bit word, and a warp vote per bit gathers that bit of every thread's
+// word into one word.  On wave64 one vote covers 64 lanes, so the step's codes
+// are arranged for it: lane l takes cell l % 32 of patch 2k + l / 32 for the
+// patch pairs k = 0..31, two pairs per word (pair 2w in the low half of word
+// w, pair 2w + 1 in the high half).  The vote on bit i of word w then holds
+// plane i % 16 of the pair 2w + i / 16: its low 32 bits are the plane word of
+// the pair's first patch, its high 32 bits that of the second.  512 votes per
+// step; each result is written into the lane that owns the patch.
+constexpr int kAblRowWords = kAblCols / 2 + 1;  // 32 words of two codes per row, plus one of padding
+
+// this lane's patch of step s as 16 plane words, by votes (the tile's codes
+// pass through `buf`, this wave's 32 x 33 words of LDS)
+__device__ __forceinline__ void ballot_patch_words(const uint16_t* __restrict__ codes, const AblGeom& g, int64_t s,
+                                                   int lane, uint32_t* buf, uint32_t (&P)[16])
 {
+    int zin;
+    const int64_t base = step_origin(g, s, &zin);
+    // the step's 32 x 64 codes into LDS, row r in words r * 33 .. r * 33 + 31
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int e = 64 * j + lane, r = e >> 3, c8 = (e & 7) * 8;  // 8 codes per lane and load
+        const uint4 t = *reinterpret_cast<const uint4*>(codes + base + (int64_t)r * g.n[2] + c8);
+        uint32_t* d = buf + r * kAblRowWords + c8 / 2;
+        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+    }
+    __syncthreads();
+    const uint16_t* b16 = reinterpret_cast<const uint16_t*>(buf);
+    const int m = lane & 31, half = lane >> 5;
+    uint32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 32; k++) {
+        const int pp = 2 * k + half;  // patch of this lane in pair k
+        const int row = 4 * (pp & 7) + (m >> 3), col = 8 * (pp >> 3) + (m & 7);
+        const uint32_t c = b16[2 * row * kAblRowWords + col];
+        if (k & 1) w[k >> 1] |= c << 16;
+        else w[k >> 1] = c;
+    }
+#pragma unroll
+    for (int b = 0; b < 16; b++) P[b] = 0u;
+#pragma unroll
+    for (int ww = 0; ww < 16; ww++) {
+#pragma unroll
+        for (int i = 0; i < 32; i++) {
+            const uint64_t v = __ballot((w[ww] >> i) & 1u);
+            const int pair = 2 * ww + (i >> 4), b = i & 15;
+            // the vote's halves go to lanes 2 pair and 2 pair + 1
+            const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+            P[b] = lane == 2 * pair ? lo : lane == 2 * pair + 1 ? hi : P[b];
+        }
+    }
+}
+
+// bitshuffle v1 with votes: one wave per step; the tile goes to HBM
+__global__ __launch_bounds__(64) void k_abl_shuffle_ballot(const uint16_t* __restrict__ codes, AblGeom g,
+                                                           uint32_t* __restrict__ tiles)
+{
+    __shared__ uint32_t buf[kAblRows * kAblRowWords];
     const int lane = threadIdx.x;
     uint32_t P[16];
-    load_patch_words(codes, g, blockIdx.x, lane, P);
+    ballot_patch_words(codes, g, blockIdx.x, lane, buf, P);
     uint32_t* t = tiles + (int64_t)blockIdx.x * 1024;
+#pragma unroll
+    for (int b = 0; b < 16; b++) t[b * 64 + lane] = P[b];
+}
+
+// flag words of a step from its 16 plane words in registers (block 16b + q
+// covers the patches, i.e. lanes, 4q .. 4q + 3); lane j < 4 gets word j
+__device__ __forceinline__ uint64_t step_flags(const uint32_t (&P)[16], int lane)
+{
     uint64_t F[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int b = 0; b < 16; b++) {
-        t[b * 64 + lane] = P[b];
-        // block 16b + q covers the patches (lanes) 4q .. 4q+3
         uint64_t m = __ballot(P[b] != 0u);
         m |= m >> 1;
         m |= m >> 2;
@@ -190,7 +251,37 @@ __global__ __launch_bounds__(64) void k_abl_shuffle_mark(const uint16_t* __restr
         for (int q = 0; q < 16; q++) f |= (uint32_t)((m >> (4 * q)) & 1u) << q;
         F[b >> 2] |= (uint64_t)f << (16 * (b & 3));
     }
-    if (lane < 4) flags[(int64_t)blockIdx.x * 4 + lane] = lane == 0 ? F[0] : lane == 1 ? F[1] : lane == 2 ? F[2] : F[3];
+    return lane == 0 ? F[0] : lane == 1 ? F[1] : lane == 2 ? F[2] : F[3];
+}
+
+// bitshuffle-mark v2 with votes
+__global__ __launch_bounds__(64) void k_abl_shuffle_mark_ballot(const uint16_t* __restrict__ codes, AblGeom g,
+                                                                uint32_t* __restrict__ tiles,
+                                                                uint64_t* __restrict__ flags)
+{
+    __shared__ uint32_t buf[kAblRows * kAblRowWords];
+    const int lane = threadIdx.x;
+    uint32_t P[16];
+    ballot_patch_words(codes, g, blockIdx.x, lane, buf, P);
+    uint32_t* t = tiles + (int64_t)blockIdx.x * 1024;
+#pragma unroll
+    for (int b = 0; b < 16; b++) t[b * 64 + lane] = P[b];
+    const uint64_t f = step_flags(P, lane);
+    if (lane < 4) flags[(int64_t)blockIdx.x * 4 + lane] = f;
+}
+
+// bitshuffle-mark v2: the flags come from the words in registers
+__global__ __launch_bounds__(64) void k_abl_shuffle_mark(const uint16_t* __restrict__ codes, AblGeom g,
+                                                         uint32_t* __restrict__ tiles, uint64_t* __restrict__ flags)
+{
+    const int lane = threadIdx.x;
+    uint32_t P[16];
+    load_patch_words(codes, g, blockIdx.x, lane, P);
+    uint32_t* t = tiles + (int64_t)blockIdx.x * 1024;
+#pragma unroll
+    for (int b = 0; b < 16; b++) t[b * 64 + lane] = P[b];
+    const uint64_t f = step_flags(P, lane);
+    if (lane < 4) flags[(int64_t)blockIdx.x * 4 + lane] = f;
 }
 
 // prefix sum: block counts per step -> exclusive offsets, in tiles of 8192
@@ -316,6 +407,25 @@ int fz_abl_mark(const uint32_t* d_tiles, const fz_dims* dims, uint64_t* d_flags,
     if (!d_tiles || !d_flags || !abl_geom(dims, &g)) return FZ_ERR_ARG;
     hipLaunchKernelGGL(k_abl_mark, dim3((unsigned)g.steps), dim3(64), 0, static_cast<hipStream_t>(stream), d_tiles, g,
                        d_flags);
+    return done() == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
+int fz_abl_bitshuffle_ballot(const uint16_t* d_codes, const fz_dims* dims, uint32_t* d_tiles, void* stream)
+{
+    AblGeom g;
+    if (!d_codes || !d_tiles || !abl_geom(dims, &g)) return FZ_ERR_ARG;
+    hipLaunchKernelGGL(k_abl_shuffle_ballot, dim3((unsigned)g.steps), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       d_codes, g, d_tiles);
+    return done() == hipSuccess ? FZ_OK : FZ_ERR_HIP;
+}
+
+int fz_abl_bitshuffle_mark_ballot(const uint16_t* d_codes, const fz_dims* dims, uint32_t* d_tiles, uint64_t* d_flags,
+                                  void* stream)
+{
+    AblGeom g;
+    if (!d_codes || !d_tiles || !d_flags || !abl_geom(dims, &g)) return FZ_ERR_ARG;
+    hipLaunchKernelGGL(k_abl_shuffle_mark_ballot, dim3((unsigned)g.steps), dim3(64), 0,
+                       static_cast<hipStream_t>(stream), d_codes, g, d_tiles, d_flags);
     return done() == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 

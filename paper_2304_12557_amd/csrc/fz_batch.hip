@@ -111,6 +111,10 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
                 loaded = true;
             }
         }
+        if (!loaded) {  // defined on every path, so that no value of this chunk stays live into the next
+#pragma unroll
+            for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
+        }
         if (!skip) chunk_place<RANK, VEC4>(J.x, J.out, g, c, wave, lane, inv, F, myflag, nout, S);
         if (tn >= total) break;
         t = tn;

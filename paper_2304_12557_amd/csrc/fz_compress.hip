@@ -52,6 +52,11 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
             l = lane_geo<RANK>(g, cn, lane);
             if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
         }
+        if (cn >= g.n_chunks || l.edge) {  // defined on every path: otherwise the values of this chunk's
+                                            // last step stay live across the placement and are spilled
+#pragma unroll
+            for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
+        }
         chunk_place<RANK, VEC4, QM>(x, out, g, c, wave, lane, inv, F, myflag, nout, S);
         if (cn >= g.n_chunks) break;
         c = cn;

@@ -218,6 +218,8 @@ def test_ablation_argument_errors():
         assert L.fz_abl_bitshuffle(p, ctypes.byref(d), p, None) == 1, shape
         assert L.fz_abl_mark(p, ctypes.byref(d), p, None) == 1, shape
         assert L.fz_abl_bitshuffle_mark(p, ctypes.byref(d), p, p, None) == 1, shape
+        assert L.fz_abl_bitshuffle_ballot(p, ctypes.byref(d), p, None) == 1, shape
+        assert L.fz_abl_bitshuffle_mark_ballot(p, ctypes.byref(d), p, p, None) == 1, shape
         assert L.fz_abl_encode(p, p, ctypes.byref(d), p, p, None) == 1, shape
     assert L.fz_abl_pred_quant(3, p, ctypes.byref(good), 100.0, p, p, None) == 1
     assert L.fz_abl_pred_quant(1, p, ctypes.byref(good), 100.0, p, None, None) == 1

@@ -1,6 +1,7 @@
 """The ablation pipeline's kernels on the GPU against the ablation oracle,
-stage by stage (all integer outputs: exact equality), for both code versions
-and both bitshuffle-mark variants."""
+stage by stage (all integer outputs: exact equality), for both code versions,
+both bitshuffle-mark variants and both transposes (in registers, and by wave
+votes as in Sec. 3.3)."""
 import numpy as np
 import pytest
 import torch
@@ -43,6 +44,18 @@ def test_stages_match_oracle(shape, seed, eb):
         torch.cuda.synchronize()
         assert np.array_equal(ab.tiles.cpu().numpy().view(np.uint32), tiles.reshape(-1)), version
         assert np.array_equal(ab.flags.cpu().numpy().view(np.uint64), flags.reshape(-1)), version
+        # the same stages with the transpose done by wave votes (Sec. 3.3)
+        for fused in (False, True):
+            ab.tiles.zero_()
+            ab.flags.zero_()
+            if fused:
+                ab.bitshuffle_mark(ballot=True)
+            else:
+                ab.bitshuffle(ballot=True)
+                ab.mark()
+            torch.cuda.synchronize()
+            assert np.array_equal(ab.tiles.cpu().numpy().view(np.uint32), tiles.reshape(-1)), (version, fused)
+            assert np.array_equal(ab.flags.cpu().numpy().view(np.uint64), flags.reshape(-1)), (version, fused)
         got_off = ab.offsets.cpu().numpy().view(np.uint64)
         assert np.array_equal(got_off, offsets), version
         n = int(offsets[-1]) * 16
