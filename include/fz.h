@@ -101,15 +101,22 @@ typedef struct {
 #define FZ_STATUS_BIT_INTERNAL 0x80000000u /* a consistency check of the library failed: the stream is invalid */
 
 /* Bytes the caller must provide as d_out of fz_compress: the worst-case
- * stream (every data block nonzero plus the escape cap), then the scratch
- * (chunk tickets and sizes, partial value ranges) and one staging slot of
- * the worst-case chunk payload per chunk, where each chunk's compacted
- * payload waits until the prefix sum has placed it: 1.1 to 1.4 times the
- * input bytes.  0 on invalid dims. */
+ * stream (every data block nonzero plus the escape cap), then the scratch:
+ * chunk tickets and sizes, partial value ranges, and the staging slots in
+ * which each compression workgroup assembles a chunk's payload until the
+ * chunk's offset is known (one slot of the worst-case chunk payload per
+ * chunk, at most 768 slots).  About 0.67 times the input bytes for a
+ * 512^3 field, 1.2 times for 64^3; a field smaller than one chunk needs the
+ * bound of one chunk (about 180 KB).  0 on invalid dims. */
 size_t fz_compress_bound(const fz_dims *dims);
 
 /* Bytes of header + chunk table + flags; depends only on the dims. */
 size_t fz_header_bytes(const fz_dims *dims);
+
+/* Worst-case size of a stream (every data block nonzero plus the escape cap
+ * of every chunk), without any scratch: about 0.56 times the input bytes.
+ * 0 on invalid dims. */
+size_t fz_stream_bound(const fz_dims *dims);
 
 /* fz_compress -- the compression pipeline of Sec. 3 (one read of the input;
  * REL mode first reads it once more for the value range).

@@ -97,6 +97,8 @@ def lib():
         L.fz_compress_bound.restype = ctypes.c_size_t
         L.fz_header_bytes.argtypes = [dp]
         L.fz_header_bytes.restype = ctypes.c_size_t
+        L.fz_stream_bound.argtypes = [dp]
+        L.fz_stream_bound.restype = ctypes.c_size_t
         L.fz_compress.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
         L.fz_compress.restype = ctypes.c_int
         L.fz_compress_timed.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp, ctypes.POINTER(FzTiming)]
@@ -163,7 +165,7 @@ def lib():
     return _LIB
 
 
-SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_compress", "fz_compress_timed", "fz_decompress", "fz_stream_info", "fz_strerror",
+SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_stream_bound", "fz_compress", "fz_compress_timed", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
@@ -195,6 +197,11 @@ def compress_bound(shape, f64=False, global_lorenzo=False):
 
 def header_bytes(shape):
     return int(lib().fz_header_bytes(ctypes.byref(dims_of(shape))))
+
+
+def stream_bound(shape):
+    """Worst-case stream bytes of a field of this shape (no scratch)."""
+    return int(lib().fz_stream_bound(ctypes.byref(dims_of(shape))))
 
 
 def _nbytes(t):

@@ -111,6 +111,13 @@ size_t fz_header_bytes(const fz_dims* dims)
     return (size_t)g.payload_off;
 }
 
+size_t fz_stream_bound(const fz_dims* dims)
+{
+    Geom g;
+    if (!geom_of(dims, &g)) return 0;
+    return (size_t)g.stream_bound;
+}
+
 int fz_compress_timed(const float* d_in, const fz_dims* dims, double eb, int eb_mode, void* d_out, void* stream,
                       const fz_timing* timing)
 {
@@ -127,8 +134,9 @@ int fz_compress_timed(const float* d_in, const fz_dims* dims, double eb, int eb_
         t.main_end = static_cast<hipEvent_t>(timing->main_end);
         t.done = static_cast<hipEvent_t>(timing->done);
     }
-    hipError_t e = launch_compress(d_in, static_cast<uint8_t*>(d_out), g, h, eb_mode, eb,
-                                   static_cast<hipStream_t>(stream), timing ? &t : nullptr);
+    uint8_t* out = static_cast<uint8_t*>(d_out);
+    hipError_t e = launch_compress(d_in, out, out + g.scratch_off, g, h, eb_mode, eb, static_cast<hipStream_t>(stream),
+                                   timing ? &t : nullptr);
     return e == hipSuccess ? FZ_OK : FZ_ERR_HIP;
 }
 

@@ -6,8 +6,8 @@
 // plan enqueues a fixed sequence of launches whatever the number of fields:
 //   init (all fields) -> value range + eb (REL fields) -> one persistent
 //   compression launch per (rank, row-alignment) class present (at most six,
-//   usually three), each over every chunk of every field of its class ->
-//   prefix sum (one workgroup per field) -> placement copy (all chunks)
+//   usually three), each over every chunk of every field of its class, which
+//   also places the chunks -> the final status word of each field
 // and a decompression plan one launch over every chunk of every field.  Each
 // field's bytes are exactly those of the per-field call: the per-chunk and
 // per-field device code is the same (fz_compress_dev.hpp,
@@ -16,7 +16,7 @@
 // runs, so a run can be captured in a hipGraph and replayed.
 //
 // The launch shapes (persistent workgroups per CU, range-pass blocks per
-// field, placement threads per chunk) come from a small autotuner that times
+// field) come from a small autotuner that times
 // the candidates on the plan's own fields; the chunk shapes are part of the
 // stream format and stay fixed, so tuning never changes a byte.
 #include <hip/hip_runtime.h>
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_batch_init(const CompressJob* __restric
         return;
     }
     const CompressJob& J = jobs[blockIdx.x];
-    init_field(J.out, J.g, J.h, threadIdx.x, 256);
+    init_field(J.out, J.out + J.g.scratch_off, J.g, J.h, threadIdx.x, 256);
 }
 
 __global__ __launch_bounds__(256) void k_batch_minmax(const CompressJob* __restrict__ jobs,
@@ -52,30 +52,34 @@ __global__ __launch_bounds__(256) void k_batch_minmax(const CompressJob* __restr
 {
     const int j = mm_job[blockIdx.x];
     const CompressJob& J = jobs[j];
-    minmax_block(J.x, J.g.n[0] * J.g.n[1] * J.g.n[2], J.out, J.g, (int64_t)blockIdx.x - J.mm0, J.mm_blocks);
+    minmax_block(J.x, J.g.n[0] * J.g.n[1] * J.g.n[2], J.out + J.g.scratch_off, J.g, (int64_t)blockIdx.x - J.mm0,
+                 J.mm_blocks);
 }
 
 __global__ __launch_bounds__(256) void k_batch_params(const CompressJob* __restrict__ jobs)
 {
     const CompressJob& J = jobs[blockIdx.x];
-    if (J.rel) params_field(J.out, J.g, J.eb, (int)J.mm_blocks);
+    if (J.rel) params_field(J.out, J.out + J.g.scratch_off, J.g, J.eb, (int)J.mm_blocks);
 }
 
 // One persistent launch per (rank, alignment) class over the chunks of every
 // field of that class: tickets run over the class's part of the chunk table,
 // which maps a ticket to its field.  Within a field the next chunk's first
 // loads are issued before the current one is placed, as in the per-field
-// kernel.  Fields whose REL pass failed are skipped.  (One instantiation per
-// launch keeps the register budget of the per-field kernel; a kernel holding
-// all six would spill.)
+// kernel, and chunks are placed as there: staged in the workgroup's slot of
+// the plan's staging area and copied to their offset one chunk later, after
+// a look-back over the field's published chunk sizes.  Fields whose REL pass
+// failed are skipped.  (One instantiation per launch keeps the register
+// budget of the per-field kernel; a kernel holding all six would spill.)
 template <int RANK, bool VEC4>
 __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __restrict__ jobs,
                                                            const int32_t* __restrict__ chunk_job, int64_t total,
-                                                           uint32_t* __restrict__ ticket)
+                                                           uint32_t* __restrict__ ticket, uint8_t* __restrict__ stage)
 {
     __shared__ CompressLds S;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint8_t* slot = stage + kStageSlotBytes * (int64_t)blockIdx.x;
     if (threadIdx.x == 0) {
         S.ticket = atomicAdd(ticket, 1u);
         S.err = 0;
@@ -86,11 +90,15 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
     int j = __builtin_amdgcn_readfirstlane(chunk_job[t]);
     float h[32], v[32];
     bool loaded = false;
+    int pend_j = -1;  // field and chunk staged in this workgroup's slot, not yet placed
+    int64_t pend_c = 0;
+    uint32_t pend_units = 0;
     for (;;) {
         const CompressJob& J = jobs[j];
         const Geom g = J.g;
         const int64_t c = t - J.chunk0;
-        const bool skip = reinterpret_cast<const Scratch*>(J.out + g.scratch_off)->pre_status != 0;
+        uint8_t* scr = J.out + g.scratch_off;
+        const bool skip = reinterpret_cast<const Scratch*>(scr)->pre_status != 0;
         const Quant inv = quant_of(J.out);
         const Lane l = lane_geo<RANK>(g, c, lane);
         if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
@@ -98,7 +106,11 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
         uint64_t F[16], myflag = 0;
         int nout = 0;
-        if (!skip) nout = chunk_layer<RANK, VEC4>(J.x, J.out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        if (!skip) nout = chunk_layer<RANK, VEC4>(J.x, scr, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        if (pend_j >= 0 && wave == 0) {  // the previous chunk's offset, while the other waves finish their layers
+            const CompressJob& P = jobs[pend_j];
+            place_lookback(P.out, P.out + P.g.scratch_off, P.g, pend_c, pend_units, S, lane);
+        }
         if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t tn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -115,25 +127,39 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
 #pragma unroll
             for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
         }
-        if (!skip) chunk_place<RANK, VEC4>(J.x, J.out, g, c, wave, lane, inv, F, myflag, nout, S);
+        uint32_t units = 0;
+        if (!skip) {
+            units = chunk_units(S);
+            if (threadIdx.x == 0)
+                publish_state(reinterpret_cast<uint64_t*>(scr + kScratchStateOff) + c,
+                              kFlagAgg | units);
+        }
+        if (pend_j >= 0) place_copy(jobs[pend_j].out, jobs[pend_j].g, pend_units, slot, S);
+        pend_j = -1;
+        if (!skip) {
+            stage_chunk<RANK, VEC4>(J.x, J.out, scr, g, c, wave, lane, inv, F, myflag, nout, S, slot);
+            pend_j = j;
+            pend_c = c;
+            pend_units = units;
+        }
         if (tn >= total) break;
         t = tn;
         j = jn;
         __syncthreads();
     }
+    if (pend_j >= 0) {
+        const CompressJob& P = jobs[pend_j];
+        if (wave == 0) place_lookback(P.out, P.out + P.g.scratch_off, P.g, pend_c, pend_units, S, lane);
+        __syncthreads();  // the staged payload and its offset are complete
+        place_copy(P.out, P.g, pend_units, slot, S);
+    }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_batch_scan(const CompressJob* __restrict__ jobs)
+// after every chunk of every field is placed: each field's final status word
+__global__ __launch_bounds__(64) void k_batch_finish(const CompressJob* __restrict__ jobs)
 {
     const CompressJob& J = jobs[blockIdx.x];
-    scan_field(J.out, J.g);
-}
-
-__global__ __launch_bounds__(256) void k_batch_move(const CompressJob* __restrict__ jobs,
-                                                    const int32_t* __restrict__ chunk_job)
-{
-    const CompressJob& J = jobs[chunk_job[blockIdx.x]];
-    move_chunk(J.out, J.g, (int64_t)blockIdx.x - J.chunkg, blockDim.x);
+    if (threadIdx.x == 0) finish_field(J.out, J.out + J.g.scratch_off);
 }
 
 __global__ __launch_bounds__(256) void k_batch_clear_err(const DecompressJob* __restrict__ jobs, int n_jobs)
@@ -168,6 +194,9 @@ int vec_key(const void* p, const Geom& g)
     return g.rank * 2 + (vec4 ? 1 : 0);
 }
 
+
+}  // namespace
+
 int cu_count()
 {
     int dev = 0, cus = 0;
@@ -175,8 +204,6 @@ int cu_count()
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 1;
     return cus;
 }
-
-}  // namespace
 
 // Host image of a plan's device tables for its current tuning: ticket
 // counters, job table, chunk -> job, range-pass block -> job.  `cap_mm` is
@@ -270,23 +297,22 @@ hipError_t plan_run(const Plan* P, hipStream_t st)
         const int64_t n = P->class_chunks[key];
         if (n == 0) continue;
         int64_t grid = (int64_t)P->cus * P->tune.per_cu;
+        if (grid > stage_slots(P->cus)) grid = stage_slots(P->cus);
         if (grid > n) grid = n;
         const int32_t* tab = P->d_chunk_job + P->class_off[key];
         uint32_t* tk = P->d_ticket + key;
+        uint8_t* sg = static_cast<uint8_t*>(P->d_stage);
         switch (key) {
-            case 7: hipLaunchKernelGGL((k_batch_compress<3, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
-            case 6: hipLaunchKernelGGL((k_batch_compress<3, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
-            case 5: hipLaunchKernelGGL((k_batch_compress<2, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
-            case 4: hipLaunchKernelGGL((k_batch_compress<2, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
-            case 3: hipLaunchKernelGGL((k_batch_compress<1, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
-            default: hipLaunchKernelGGL((k_batch_compress<1, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk); break;
+            case 7: hipLaunchKernelGGL((k_batch_compress<3, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
+            case 6: hipLaunchKernelGGL((k_batch_compress<3, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
+            case 5: hipLaunchKernelGGL((k_batch_compress<2, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
+            case 4: hipLaunchKernelGGL((k_batch_compress<2, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
+            case 3: hipLaunchKernelGGL((k_batch_compress<1, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
+            default: hipLaunchKernelGGL((k_batch_compress<1, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs, tab, n, tk, sg); break;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_batch_scan, dim3(P->n_jobs), dim3(kScanThreads), 0, st, jobs);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_move, dim3((unsigned)P->total_chunks), dim3(P->tune.move_threads), 0, st, jobs,
-                       P->d_chunk_job);
+    hipLaunchKernelGGL(k_batch_finish, dim3(P->n_jobs), dim3(64), 0, st, jobs);
     return hipGetLastError();
 }
 
@@ -298,8 +324,9 @@ int plan_compress(Plan* Pp, int n, const fz_compress_job* jobs)
     P.n_jobs = n;
     for (int k = 0; k < 8; k++) P.class_off[k] = P.class_chunks[k] = 0;
     P.dev = nullptr;
+    P.d_stage = nullptr;
     P.cus = cu_count();
-    P.tune = Tuning{2, kMinmaxBlocks, 256};
+    P.tune = Tuning{2, kMinmaxBlocks};
     P.any_rel = false;
     P.mm_max = 0;
     P.cjobs.clear();
@@ -347,8 +374,9 @@ int plan_decompress(Plan* Pp, int n, const fz_decompress_job* jobs)
     P.n_jobs = n;
     for (int k = 0; k < 8; k++) P.class_off[k] = P.class_chunks[k] = 0;
     P.dev = nullptr;
+    P.d_stage = nullptr;
     P.cus = cu_count();
-    P.tune = Tuning{2, kMinmaxBlocks, 256};
+    P.tune = Tuning{2, kMinmaxBlocks};
     P.any_rel = false;
     P.mm_max = 0;
     P.cjobs.clear();
@@ -395,6 +423,10 @@ int create(fz_batch** out, bool compress, int n, const void* jobs)
     int rc = compress ? plan_compress(&b->p, n, static_cast<const fz_compress_job*>(jobs))
                       : plan_decompress(&b->p, n, static_cast<const fz_decompress_job*>(jobs));
     if (rc == FZ_OK) rc = upload(&b->p);
+    if (rc == FZ_OK && b->p.compress && hipMalloc(&b->p.d_stage, stage_bytes(b->p.cus)) != hipSuccess) {
+        b->p.d_stage = nullptr;
+        rc = FZ_ERR_HIP;
+    }
     if (rc != FZ_OK) {
         if (b->p.dev) (void)hipFree(b->p.dev);
         delete b;
@@ -436,8 +468,7 @@ int fz_batch_tune(fz_batch* b, void* stream)
         (void)hipEventDestroy(e0);
         return FZ_ERR_HIP;
     }
-    const Tuning cands[] = {{2, kMinmaxBlocks, 256}, {1, kMinmaxBlocks, 256}, {2, 512, 256}, {2, kMinmaxBlocks, 64},
-                            {2, 512, 64}};
+    const Tuning cands[] = {{2, kMinmaxBlocks}, {1, kMinmaxBlocks}, {2, 512}, {1, 512}};
     Tuning best = P.tune;
     float best_ms = 1e30f;
     int rc = FZ_OK;
@@ -471,6 +502,7 @@ int fz_batch_destroy(fz_batch* b)
     if (!b) return FZ_ERR_ARG;
     int rc = FZ_OK;
     if (b->p.dev && hipFree(b->p.dev) != hipSuccess) rc = FZ_ERR_HIP;
+    if (b->p.d_stage && hipFree(b->p.d_stage) != hipSuccess) rc = FZ_ERR_HIP;
     delete b;
     return rc;
 }

@@ -40,10 +40,17 @@ struct DecompressJob {
 };
 
 struct Tuning {
-    int per_cu;      // persistent compression workgroups per CU (1 or 2)
-    int mm_cap;      // range-pass blocks per field, at most
-    int move_threads;
+    int per_cu;  // persistent compression workgroups per CU (1 or 2)
+    int mm_cap;  // range-pass blocks per field, at most
 };
+
+// compute units of the current device (1 if unknown)
+int cu_count();
+
+// staging slots of a compression plan (one per persistent workgroup) and
+// their bytes, for a device with `cus` compute units
+inline int stage_slots(int cus) { return 2 * cus < kStageSlots ? 2 * cus : kStageSlots; }
+inline size_t stage_bytes(int cus) { return (size_t)stage_slots(cus) * (size_t)kStageSlotBytes; }
 
 struct Plan {
     bool compress;
@@ -63,6 +70,7 @@ struct Plan {
     void* d_jobs;
     int32_t* d_chunk_job;
     int32_t* d_mm_job;
+    void* d_stage;  // compression: stage_bytes(cus) of staging slots (the plan's own, or its server slot's)
 };
 
 // Build a plan from jobs on the host (validates them; no device work).

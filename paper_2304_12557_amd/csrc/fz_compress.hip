@@ -3,12 +3,13 @@
 // k_compress: persistent workgroups of 4 waves take the chunks of one field by
 // ticket; each chunk's layers, flags and staged payload come from the device
 // code in fz_compress_dev.hpp.  The next chunk's first loads are issued
-// before the current chunk is placed, and no chunk waits for another.
-//
-// k_scan + k_move: the device-wide prefix sum over the chunk sizes and the
-// final compaction (Sec. 3.4): one workgroup scans the published sizes into
-// the chunk table, then one workgroup per chunk copies its staged payload to
-// its offset.  REL mode runs k_minmax + k_params first (the value range).
+// before the current chunk is placed.  The device-wide prefix sum of the
+// encoder (Sec. 3.4) is a look-back over published chunk sizes: a chunk is
+// staged in its workgroup's slot and placed one chunk later, when the sizes
+// of the chunks before it are almost always published, so the look-back
+// rarely waits; then the slot, still in the cache, is copied to the chunk's
+// offset.  k_finish settles the status word.  REL mode runs k_minmax +
+// k_params first (the value range).
 #include <hip/hip_runtime.h>
 
 #include "fz.h"
@@ -18,14 +19,17 @@
 namespace fz {
 
 template <int RANK, bool VEC4, int QM>
-__global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out, Geom g)
+__global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out,
+                                                     uint8_t* __restrict__ scratch, Geom g)
 {
     __shared__ CompressLds S;
-    Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
+    Scratch* scr = reinterpret_cast<Scratch*>(scratch);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keep it scalar
     if (scr->pre_status) return;  // set before this launch: uniform across the grid
     const Quant inv = quant_of(out);
+    uint64_t* state = reinterpret_cast<uint64_t*>(scratch + kScratchStateOff);
+    uint8_t* slot = scratch + g.scr_stage + kStageSlotBytes * (int64_t)blockIdx.x;
 
     if (threadIdx.x == 0) {
         S.ticket = atomicAdd(&scr->ticket, 1u);
@@ -37,6 +41,8 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     float h[32], v[32];
     Lane l = lane_geo<RANK>(g, c, lane);
     if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
+    int64_t pend = -1;  // the chunk staged in this workgroup's slot, not yet placed
+    uint32_t pend_units = 0;
 
     for (;;) {
         // the next chunk's ticket, taken now so that its return has the whole
@@ -44,7 +50,9 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         uint32_t tk;  // thread 0 only: a value on the other lanes would need a copy that waits for the atomic
         if (threadIdx.x == 0) tk = atomicAdd(&scr->ticket, 1u);
         uint64_t F[16], myflag;
-        const int nout = chunk_layer<RANK, VEC4, QM>(x, out, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        const int nout = chunk_layer<RANK, VEC4, QM>(x, scratch, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        // the previous chunk's offset: wave 0 looks back while the other waves finish their layers
+        if (pend >= 0 && wave == 0) place_lookback(out, scratch, g, pend, pend_units, S, lane);
         if (threadIdx.x == 0) S.ticket = tk;
         __syncthreads();
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -57,31 +65,45 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
 #pragma unroll
             for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
         }
-        chunk_place<RANK, VEC4, QM>(x, out, g, c, wave, lane, inv, F, myflag, nout, S);
+        // this chunk's size goes out first, so that no look-back waits on it
+        // while this workgroup places its previous chunk
+        const uint32_t units = chunk_units(S);
+        if (threadIdx.x == 0) publish_state(state + c, kFlagAgg | units);
+        if (pend >= 0) place_copy(out, g, pend_units, slot, S);
+        stage_chunk<RANK, VEC4, QM>(x, out, scratch, g, c, wave, lane, inv, F, myflag, nout, S, slot);
+        pend = c;
+        pend_units = units;
         if (cn >= g.n_chunks) break;
         c = cn;
         __syncthreads();  // the LDS counts and bricks are reused by the next chunk
     }
+    if (wave == 0) place_lookback(out, scratch, g, pend, pend_units, S, lane);
+    __syncthreads();  // the staged payload and its offset are complete
+    place_copy(out, g, pend_units, slot, S);
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan(uint8_t* __restrict__ out, Geom g) { scan_field(out, g); }
-
-__global__ __launch_bounds__(256) void k_move(uint8_t* __restrict__ out, Geom g) { move_chunk(out, g, blockIdx.x, 256); }
-
-__global__ __launch_bounds__(256) void k_init(uint8_t* __restrict__ out, Geom g, HeaderImage h)
+// after every chunk of the field is placed: the final status word
+__global__ __launch_bounds__(64) void k_finish(uint8_t* __restrict__ out, const uint8_t* __restrict__ scratch)
 {
-    init_field(out, g, h, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+    if (threadIdx.x == 0) finish_field(out, scratch);
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ out,
+__global__ __launch_bounds__(256) void k_init(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, Geom g,
+                                              HeaderImage h)
+{
+    init_field(out, scratch, g, h, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ scratch,
                                                 Geom g)
 {
-    minmax_block(x, n, out, g, blockIdx.x, gridDim.x);
+    minmax_block(x, n, scratch, g, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_params(uint8_t* __restrict__ out, Geom g, double eb, int nparts)
+__global__ __launch_bounds__(256) void k_params(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, Geom g,
+                                                double eb, int nparts)
 {
-    params_field(out, g, eb, nparts);
+    params_field(out, scratch, g, eb, nparts);
 }
 
 // ----------------------------------------------------------------- launch
@@ -95,7 +117,8 @@ int64_t minmax_blocks(int64_t n)
 static hipError_t mark(hipEvent_t e, hipStream_t st) { return e ? hipEventRecord(e, st) : hipSuccess; }
 
 template <int RANK, bool VEC4, int QM>
-static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipStream_t st, const Timing* t = nullptr)
+static hipError_t launch_rank(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, hipStream_t st,
+                              const Timing* t = nullptr)
 {
     // persistent grid: as many workgroups as stay resident, at most one per chunk
     int dev = 0, cus = 0, per_cu = 0;
@@ -104,107 +127,101 @@ static hipError_t launch_rank(const float* x, uint8_t* out, const Geom& g, hipSt
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compress<RANK, VEC4, QM>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int64_t resident = (int64_t)cus * per_cu;
-    const int64_t grid = g.n_chunks < resident ? g.n_chunks : resident;
+    int64_t grid = (int64_t)cus * per_cu;  // one staging slot per workgroup: at most kStageSlots
+    if (grid > kStageSlots) grid = kStageSlots;
+    if (grid > g.n_chunks) grid = g.n_chunks;
     hipError_t e;
     if (t && (e = mark(t->main_begin, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, g);
+    hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, scr, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t && (e = mark(t->main_end, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, out, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_move, dim3((unsigned)g.n_chunks), dim3(256), 0, st, out, g);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, out, scr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return t ? mark(t->done, st) : hipSuccess;
 }
 
-static hipError_t launch_init(uint8_t* out, const Geom& g, const HeaderImage& h, hipStream_t st)
+static hipError_t launch_init(uint8_t* out, uint8_t* scr, const Geom& g, const HeaderImage& h, hipStream_t st)
 {
     const int64_t init_threads = g.n_chunks > kHeaderBytes / 4 ? g.n_chunks : kHeaderBytes / 4;
     const unsigned init_blocks = (unsigned)((init_threads + 255) / 256 < 1024 ? (init_threads + 255) / 256 : 1024);
-    hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, out, g, h);
+    hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, out, scr, g, h);
     return hipGetLastError();
 }
 
-// the compression kernel on the integer buffer at g.q_off
+// the compression kernel on the integer buffer at g.q_off (scratch inside the output buffer)
 static hipError_t launch_main_int(uint8_t* out, const Geom& g, hipStream_t st)
 {
     // the integer buffer is 256-byte aligned: whole-vector loads whenever the rows allow them
-    const int32_t* q = reinterpret_cast<const int32_t*>(out + g.q_off);
-    const float* qf = reinterpret_cast<const float*>(q);
+    const float* qf = reinterpret_cast<const float*>(out + g.q_off);
+    uint8_t* scr = out + g.scratch_off;
     const bool vec4 = g.rank == 1 || (g.n[g.rank - 1] & 3) == 0;
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true, kQuantInt>(qf, out, g, st);
-        case 6: return launch_rank<3, false, kQuantInt>(qf, out, g, st);
-        case 5: return launch_rank<2, true, kQuantInt>(qf, out, g, st);
-        case 4: return launch_rank<2, false, kQuantInt>(qf, out, g, st);
-        case 3: return launch_rank<1, true, kQuantInt>(qf, out, g, st);
-        default: return launch_rank<1, false, kQuantInt>(qf, out, g, st);
+        case 7: return launch_rank<3, true, kQuantInt>(qf, out, scr, g, st);
+        case 6: return launch_rank<3, false, kQuantInt>(qf, out, scr, g, st);
+        case 5: return launch_rank<2, true, kQuantInt>(qf, out, scr, g, st);
+        case 4: return launch_rank<2, false, kQuantInt>(qf, out, scr, g, st);
+        case 3: return launch_rank<1, true, kQuantInt>(qf, out, scr, g, st);
+        default: return launch_rank<1, false, kQuantInt>(qf, out, scr, g, st);
     }
 }
 
 hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
                                double eb, hipStream_t st)
 {
-    hipError_t e = launch_init(out, g, h, st);
+    hipError_t e = launch_init(out, out + g.scratch_off, g, h, st);
     if (e != hipSuccess) return e;
     if ((e = launch_f64_front(x, out, g, mode, eb, st)) != hipSuccess) return e;
     return launch_main_int(out, g, st);
 }
 
-static hipError_t launch_range(const float* x, uint8_t* out, const Geom& g, double eb, hipStream_t st)
+// the value range and the eb parameters of the relative bound
+static hipError_t launch_range(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, double eb, hipStream_t st)
 {
     const int64_t n = g.n[0] * g.n[1] * g.n[2];
     const int64_t blocks = minmax_blocks(n);
-    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
+    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, scr, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, g, eb, (int)blocks);
+    hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, scr, g, eb, (int)blocks);
     return hipGetLastError();
 }
 
 hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode,
                                   double eb, hipStream_t st)
 {
-    hipError_t e = launch_init(out, g, h, st);
+    uint8_t* scr = out + g.scratch_off;
+    hipError_t e = launch_init(out, scr, g, h, st);
     if (e != hipSuccess) return e;
-    if (mode == FZ_EB_REL && (e = launch_range(x, out, g, eb, st)) != hipSuccess) return e;
+    if (mode == FZ_EB_REL && (e = launch_range(x, out, scr, g, eb, st)) != hipSuccess) return e;
     if ((e = launch_face(x, out, g, st)) != hipSuccess) return e;
     return launch_main_int(out, g, st);
 }
 
-hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
-                           hipStream_t st, const Timing* t)
+hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, const HeaderImage& h, int mode,
+                           double eb, hipStream_t st, const Timing* t)
 {
-    hipError_t e = launch_init(out, g, h, st);
+    hipError_t e = launch_init(out, scr, g, h, st);
     if (e != hipSuccess) return e;
     if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
-    if (mode == FZ_EB_REL) {
-        const int64_t n = g.n[0] * g.n[1] * g.n[2];
-        const int64_t blocks = minmax_blocks(n);
-        hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, g);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, g, eb, (int)blocks);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if (mode == FZ_EB_REL && (e = launch_range(x, out, scr, g, eb, st)) != hipSuccess) return e;
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     if (mode == FZ_EB_PWREL) {
         switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-            case 7: return launch_rank<3, true, kQuantPw>(x, out, g, st, t);
-            case 6: return launch_rank<3, false, kQuantPw>(x, out, g, st, t);
-            case 5: return launch_rank<2, true, kQuantPw>(x, out, g, st, t);
-            case 4: return launch_rank<2, false, kQuantPw>(x, out, g, st, t);
-            case 3: return launch_rank<1, true, kQuantPw>(x, out, g, st, t);
-            default: return launch_rank<1, false, kQuantPw>(x, out, g, st, t);
+            case 7: return launch_rank<3, true, kQuantPw>(x, out, scr, g, st, t);
+            case 6: return launch_rank<3, false, kQuantPw>(x, out, scr, g, st, t);
+            case 5: return launch_rank<2, true, kQuantPw>(x, out, scr, g, st, t);
+            case 4: return launch_rank<2, false, kQuantPw>(x, out, scr, g, st, t);
+            case 3: return launch_rank<1, true, kQuantPw>(x, out, scr, g, st, t);
+            default: return launch_rank<1, false, kQuantPw>(x, out, scr, g, st, t);
         }
     }
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true, kQuantGrid>(x, out, g, st, t);
-        case 6: return launch_rank<3, false, kQuantGrid>(x, out, g, st, t);
-        case 5: return launch_rank<2, true, kQuantGrid>(x, out, g, st, t);
-        case 4: return launch_rank<2, false, kQuantGrid>(x, out, g, st, t);
-        case 3: return launch_rank<1, true, kQuantGrid>(x, out, g, st, t);
-        default: return launch_rank<1, false, kQuantGrid>(x, out, g, st, t);
+        case 7: return launch_rank<3, true, kQuantGrid>(x, out, scr, g, st, t);
+        case 6: return launch_rank<3, false, kQuantGrid>(x, out, scr, g, st, t);
+        case 5: return launch_rank<2, true, kQuantGrid>(x, out, scr, g, st, t);
+        case 4: return launch_rank<2, false, kQuantGrid>(x, out, scr, g, st, t);
+        case 3: return launch_rank<1, true, kQuantGrid>(x, out, scr, g, st, t);
+        default: return launch_rank<1, false, kQuantGrid>(x, out, scr, g, st, t);
     }
 }
 

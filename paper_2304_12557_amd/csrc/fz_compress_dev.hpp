@@ -10,10 +10,12 @@
 // registers (the bitshuffle of Sec. 3.3).  After its 4 steps a lane holds 16
 // bricks (one per bit plane); a ballot per plane gives the bit flags of the
 // zero-block encoder (Sec. 3.4), and the nonzero bricks are compacted into
-// the chunk's staging slot with coalesced 16-byte writes.  A layer whose
+// the workgroup's staging slot with coalesced 16-byte writes.  A layer whose
 // deltas need escapes is computed again out of line; its (index, delta) pairs
 // are written after the workgroup barrier, once every layer's count is known,
-// straight to their place behind the chunk's bricks.
+// straight to their place behind the chunk's bricks.  One chunk later, when
+// a look-back over the published chunk sizes (the device-wide prefix sum of
+// Sec. 3.4) has given the chunk its offset, the slot is copied there.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -542,11 +544,11 @@ __device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom
 // call: inlined, its registers would push the fast path into spills, while
 // as a call the register saves happen only on this path.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
-__device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
+__device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const uint8_t* scr,
                                             int64_t c, int k, Quant inv, int lane, uint32_t* Wl, uint32_t* pairs,
                                             int room)
 {
-    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
+    const Geom g = *reinterpret_cast<const Geom*>(scr + kScratchGeomOff);
     const Lane l = lane_geo<RANK>(g, c, lane);
     float h[32], v[32];
     prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
@@ -561,10 +563,10 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
 // Rare path: a step saw NaN/Inf or |x*inv| >= 2^31.  Re-read the layer's
 // cells and classify them the way the format defines the status bits
 // (halo values belong to the previous layer, which reports them).
-__device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const uint8_t* out, int64_t scratch_off,
+__device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x, const uint8_t* scr,
                                                  int64_t c, int k, Quant inv, int lane)
 {
-    const Geom g = *reinterpret_cast<const Geom*>(out + scratch_off + kScratchGeomOff);
+    const Geom g = *reinterpret_cast<const Geom*>(scr + kScratchGeomOff);
     int64_t o[3], e[3];
     chunk_box(g, c, o, e);
     uint32_t err = 0;
@@ -591,6 +593,7 @@ struct CompressLds {
     uint32_t err;
     uint32_t nnz[kLayers], nout[kLayers];
     uint64_t ticket;
+    uint64_t excl;  // offset of the chunk being placed (16-B units), from the look-back
     // per wave: the bricks of its layer (as plane-step words)
     uint32_t w[kLayers][kPlanes * 4 * 64];
 };
@@ -598,16 +601,16 @@ struct CompressLds {
 // Tail of a wave's layer: the data-dependent status bits (NaN/Inf or an
 // overflowing product, seen in facc), the flags of the
 // zero-block encoder (one ballot per bit plane, F; lane b < 16 gets F[b] in
-// `myflag`, which chunk_place stores), and the layer's counts in S.  Returns
+// `myflag`, which stage_chunk stores), and the layer's counts in S.  Returns
 // the layer's escape count.
-__device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+__device__ __forceinline__ int layer_flags(const float* __restrict__ x, const uint8_t* __restrict__ scr, const Geom& g,
                                            int64_t c, int wave, int lane, Quant inv, const uint32_t (&nz)[16],
                                            float facc, const EscapeLog& log, CompressLds& S, uint64_t (&F)[16],
                                            uint64_t& myflag)
 {
     uint32_t err = 0;
     if (__ballot(!(facc < 2147483648.0f))) {  // NaN, Inf or |x*inv| >= 2^31 somewhere in the layer
-        err = classify_errors(x, out, g.scratch_off, c, wave, inv, lane);
+        err = classify_errors(x, scr, c, wave, inv, lane);
 #pragma unroll
         for (int sh = 32; sh > 0; sh >>= 1) err |= (uint32_t)__shfl_xor((int)err, sh);
     }
@@ -636,7 +639,7 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, uint8_t*
 // loads its own).  F receives the layer's per-plane ballots and `myflag` the
 // flag word lane b < 16 stores; returns the layer's escape count.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
-__device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+__device__ __forceinline__ int chunk_layer(const float* __restrict__ x, const uint8_t* __restrict__ scr, const Geom& g,
                                            int64_t c, const Lane& l, int wave, int lane, Quant inv, float (&h)[32],
                                            float (&v)[32], CompressLds& S, uint64_t (&F)[16], uint64_t& myflag)
 {
@@ -656,7 +659,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
             }
         }
         if (slow) {  // edge chunk, or escapes to log
-            const uint64_t r = layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, nullptr, 0);
+            const uint64_t r = layer_slow<RANK, VEC4, QM>(x, scr, c, wave, inv, lane, Wl, nullptr, 0);
             log.count = (int)(r >> 32);
             facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
 #pragma unroll
@@ -668,36 +671,100 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, uint8_t*
 #pragma unroll
         for (int b = 0; b < 16; b++) nz[b] = 0u;
     }
-    return layer_flags(x, out, g, c, wave, lane, inv, nz, facc, log, S, F, myflag);
+    return layer_flags(x, scr, g, c, wave, lane, inv, nz, facc, log, S, F, myflag);
+}
+
+// Payload size of the chunk in S (16-B units): its nonzero bricks, then its
+// escape pairs padded to 16 bytes (none when the chunk holds more than
+// kChunkOutlierCap escapes: the stream then carries the OUTLIER_CAP status).
+__device__ __forceinline__ uint32_t chunk_units(const CompressLds& S)
+{
+    const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
+    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];  // each at most 8192: no overflow
+    const uint32_t kept = to > (uint32_t)kChunkOutlierCap ? 0u : to;
+    return tn + (kept + 1) / 2;
+}
+
+// Chunk state words are read and written with agent-scope atomics: the
+// workgroups that publish and read them run on different XCDs, whose L2
+// caches are not coherent with one another.
+__device__ __forceinline__ void publish_state(uint64_t* p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t peek_state(const uint64_t* p)
+{
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// polls of a look-back before it gives up (each poll sleeps about 64 cycles
+// and waits for a load that bypasses the L2; far beyond any real wait)
+constexpr int kLookbackSpins = 1 << 18;
+
+// Exclusive prefix of chunk c's payload size (Sec. 3.4: the offset of its
+// data blocks), by one wave: the published states of chunks c-1, c-2, ... are
+// read 64 at a time and summed back to the nearest chunk that published its
+// inclusive prefix.  Chunks that have not published their size yet are polled
+// until they do (every chunk before c was taken by a running workgroup, which
+// publishes its size without waiting for anything).  Returns false if the
+// polls ran out (the stream is then marked with an internal error).
+__device__ __forceinline__ bool lookback(const uint64_t* state, int64_t c, int lane, uint64_t& excl)
+{
+    uint64_t sum = 0;
+    for (int64_t hi = c; hi > 0; hi -= 64) {
+        const int64_t i = hi - 1 - lane;  // lane 0 reads the nearest chunk
+        uint64_t v = i >= 0 ? peek_state(state + i) : kFlagIncl;  // before chunk 0: inclusive prefix 0
+        for (int spin = 0;; spin++) {
+            const uint64_t incl = __ballot((v & ~kValueMask) == kFlagIncl);
+            const int first = incl ? __builtin_ctzll(incl) : 64;
+            const uint64_t below = first == 64 ? ~0ull : (1ull << first) - 1;
+            const uint64_t miss = __ballot((v & ~kValueMask) == 0) & below;
+            if (!miss) {
+                uint64_t t = lane <= first ? (v & kValueMask) : 0;
+#pragma unroll
+                for (int sh = 32; sh > 0; sh >>= 1) t += __shfl_xor(t, sh);
+                sum += t;
+                if (incl) {
+                    excl = sum;
+                    return true;
+                }
+                break;
+            }
+            if (spin >= kLookbackSpins) {
+                excl = 0;
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((miss >> lane) & 1ull) v = peek_state(state + i);
+        }
+    }
+    excl = sum;
+    return true;
 }
 
 // After a workgroup barrier that follows chunk_layer on all 4 waves: the
 // layer's flags go to the stream (stored only here, so that no wait before
-// the barrier covers them), the chunk's size to its state word (the
-// placement kernels turn the sizes into offsets), its escape count to the
-// table, the counts to the header, and its payload is assembled in its
-// staging slot: nonzero bricks in (layer, plane, patch) order, then the
-// escape pairs padded to 16 bytes.  A chunk may hold kChunkOutlierCap
-// escapes wherever they fall; past that the stream carries the OUTLIER_CAP
-// status and no pairs are written.  A layer with escapes is computed again
-// out of line (its first pass kept only the count) and writes its pairs
-// behind those of the layers before it.
+// the barrier covers them), the chunk's escape count to the table, the counts
+// to the header, and its payload is assembled in the workgroup's staging slot:
+// nonzero bricks in (layer, plane, patch) order, then the escape pairs padded
+// to 16 bytes.  A chunk may hold kChunkOutlierCap escapes wherever they fall;
+// past that the stream carries the OUTLIER_CAP status and no pairs are
+// written.  A layer with escapes is computed again out of line (its first
+// pass kept only the count) and writes its pairs behind those of the layers
+// before it.  The chunk's size was published right after the barrier.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
-__device__ __forceinline__ void chunk_place(const float* __restrict__ x, uint8_t* __restrict__ out, const Geom& g,
+__device__ __forceinline__ void stage_chunk(const float* __restrict__ x, uint8_t* __restrict__ out,
+                                            const uint8_t* __restrict__ scr, const Geom& g,
                                             int64_t c, int wave, int lane, Quant inv, const uint64_t (&F)[16],
-                                            uint64_t myflag, int nout, CompressLds& S)
+                                            uint64_t myflag, int nout, CompressLds& S, uint8_t* __restrict__ slot)
 {
     if (lane < 16)
         reinterpret_cast<uint64_t*>(out + g.flags_off + (int64_t)kFlagBytesPerChunk * c + 128 * wave)[lane] = myflag;
-    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
     const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
-    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];  // each at most 8192: no overflow
+    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];
     const bool capped = to > (uint32_t)kChunkOutlierCap;
     const uint32_t kept = capped ? 0u : to;
-    uint8_t* slot = out + g.stage_off + kStageSlotBytes * c;
     if (threadIdx.x == 0) {
-        const uint64_t units = tn + (kept + 1) / 2;
-        state[c] = kFlagAgg | units;
         reinterpret_cast<uint32_t*>(out + g.table_off + 8 * c)[1] = kept;
         atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNnz), (unsigned long long)tn);
         atomicAdd(reinterpret_cast<unsigned long long*>(out + kOffNout), (unsigned long long)kept);
@@ -723,8 +790,48 @@ __device__ __forceinline__ void chunk_place(const float* __restrict__ x, uint8_t
         uint32_t first = 0;
         for (int w = 0; w < wave; w++) first += S.nout[w];
         uint32_t* pairs = reinterpret_cast<uint32_t*>(slot + 16 * tn) + 2 * first;
-        (void)layer_slow<RANK, VEC4, QM>(x, out, g.scratch_off, c, wave, inv, lane, Wl, pairs, nout);
+        (void)layer_slow<RANK, VEC4, QM>(x, scr, c, wave, inv, lane, Wl, pairs, nout);
     }
+}
+
+// Placement of chunk p, staged in a workgroup's slot with `units` 16-B units
+// of payload, in two parts.  place_lookback, by one wave (any time after the
+// staging, before a barrier that precedes place_copy): the look-back finds
+// the offset, thread 0 publishes the inclusive prefix, writes the offset to
+// the table and, for the field's last chunk, the stream's total size to the
+// header, and leaves the offset in S.excl.  A failed look-back marks the
+// stream with an internal error and still publishes (as if at offset 0), so
+// that no later chunk waits on this one; every offset stays inside the
+// stream's bound.
+__device__ __forceinline__ void place_lookback(uint8_t* __restrict__ out, uint8_t* __restrict__ scr, const Geom& g,
+                                               int64_t p, uint32_t units, CompressLds& S, int lane)
+{
+    uint64_t* state = reinterpret_cast<uint64_t*>(scr + kScratchStateOff);
+    uint64_t excl;
+    const bool ok = lookback(state, p, lane, excl);
+    if (lane == 0) {
+        if (!ok) atomicOr(reinterpret_cast<uint32_t*>(out + kOffStatus), kErrInternal);
+        const uint64_t at = ok ? excl : 0;
+        S.excl = ok ? excl : ~0ull;
+        publish_state(state + p, kFlagIncl | (at + units));
+        reinterpret_cast<uint32_t*>(out + g.table_off)[2 * p] = (uint32_t)at;
+        if (p == g.n_chunks - 1) *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * (at + units);
+    }
+}
+
+// place_copy, by the whole workgroup: the staged payload goes to its offset
+// (read from the cache: the slot was written one chunk earlier).  Ends with a
+// barrier, so the slot may be written again.
+__device__ __forceinline__ void place_copy(uint8_t* __restrict__ out, const Geom& g, uint32_t units,
+                                           const uint8_t* __restrict__ slot, const CompressLds& S)
+{
+    const uint64_t excl = S.excl;
+    if (excl != ~0ull) {
+        const uint4* src = reinterpret_cast<const uint4*>(slot);
+        uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + excl;
+        for (uint32_t i = threadIdx.x; i < units; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------- per-field pipeline steps
@@ -733,18 +840,19 @@ __device__ __forceinline__ void chunk_place(const float* __restrict__ x, uint8_t
 
 // Header, table padding, scratch and chunk states of one field, by `nthreads`
 // threads numbered `tid`.
-__device__ __forceinline__ void init_field(uint8_t* __restrict__ out, const Geom& g, const HeaderImage& h, int64_t tid,
+__device__ __forceinline__ void init_field(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, const Geom& g,
+                                           const HeaderImage& h, int64_t tid,
                                            int64_t nthreads)
 {
     if (tid < kHeaderBytes / 4) reinterpret_cast<uint32_t*>(out)[tid] = h.w[tid];
     if (tid == 0 && (g.n_chunks & 1))  // the chunk table is padded to 16 bytes with zeros
         *reinterpret_cast<uint2*>(out + g.table_off + 8 * g.n_chunks) = make_uint2(0u, 0u);
-    uint32_t* scr = reinterpret_cast<uint32_t*>(out + g.scratch_off);
+    uint32_t* scr = reinterpret_cast<uint32_t*>(scratch);
     if (tid < kScratchGeomOff / 4) scr[tid] = 0u;
     static_assert(sizeof(Geom) % 4 == 0 && kScratchGeomOff + sizeof(Geom) <= kScratchStateOff, "scratch layout");
     if (tid < (int64_t)(sizeof(Geom) / 4))
         scr[kScratchGeomOff / 4 + tid] = reinterpret_cast<const uint32_t*>(&g)[tid];
-    uint64_t* state = reinterpret_cast<uint64_t*>(out + g.scratch_off + kScratchStateOff);
+    uint64_t* state = reinterpret_cast<uint64_t*>(scratch + kScratchStateOff);
     for (int64_t i = tid; i < g.n_chunks; i += nthreads) state[i] = 0;
 }
 
@@ -752,7 +860,7 @@ __device__ __forceinline__ void init_field(uint8_t* __restrict__ out, const Geom
 // relative error bound: the blocks walk the field from its end so that its
 // beginning, which compression reads first, is the most recently touched
 // data.  The partial (min key, max key, non-finite) goes to the scratch.
-__device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ out,
+__device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ scr,
                                              const Geom& g, int64_t blk, int64_t nblk)
 {
     __shared__ uint32_t s_red[3][4];
@@ -793,7 +901,7 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
     if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t* part = reinterpret_cast<uint32_t*>(out + g.minmax_off) + 4 * blk;
+        uint32_t* part = reinterpret_cast<uint32_t*>(scr + g.scr_minmax) + 4 * blk;
         part[0] = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
         part[1] = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
         part[2] = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
@@ -804,11 +912,12 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
 // block of 256 threads): eb_abs = eb * (vmax - vmin) in double (a constant
 // field uses eb * |vmax|, or eb if that is 0), ebx2 = fp32(2 eb_abs),
 // inv = fp32(1 / (double)ebx2).
-__device__ __forceinline__ void params_field(uint8_t* __restrict__ out, const Geom& g, double eb, int nparts)
+__device__ __forceinline__ void params_field(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, const Geom& g,
+                                             double eb, int nparts)
 {
     __shared__ uint32_t s_red[3][4];
-    Scratch* scr = reinterpret_cast<Scratch*>(out + g.scratch_off);
-    const uint32_t* part = reinterpret_cast<const uint32_t*>(out + g.minmax_off);
+    Scratch* scr = reinterpret_cast<Scratch*>(scratch);
+    const uint32_t* part = reinterpret_cast<const uint32_t*>(scratch + g.scr_minmax);
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
         lo = min(lo, part[4 * i]);
@@ -858,81 +967,17 @@ __device__ __forceinline__ void params_field(uint8_t* __restrict__ out, const Ge
     scr->pre_status = status;
 }
 
-// Device-wide exclusive prefix sum over one field's chunk sizes (Sec. 3.4),
-// one workgroup of kScanThreads threads walking the sizes in tiles: the
-// offsets go to the chunk table, the payload size to the header.
-constexpr int kScanThreads = 1024, kScanPerThread = 8;
-
-__device__ __forceinline__ void scan_field(uint8_t* __restrict__ out, const Geom& g)
+// End of one field's compression, after every chunk is placed (a launch of
+// its own): a failed prequantization anywhere (NaN/Inf, overflow) ends the
+// pipeline before the encoder, so the escape-cap bit of chunks that went on
+// counts only when no such bit is set.
+__device__ __forceinline__ void finish_field(uint8_t* __restrict__ out, const uint8_t* __restrict__ scratch)
 {
-    __shared__ uint32_t s_wave[kScanThreads / 64];
-    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
-    if (scr->pre_status) return;  // nothing was compressed (uniform)
-    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    uint32_t* table = reinterpret_cast<uint32_t*>(out + g.table_off);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint64_t carry = 0;
-    bool bad = false;
-    for (int64_t base = 0; base < g.n_chunks; base += kScanThreads * kScanPerThread) {
-        const int64_t i0 = base + (int64_t)tid * kScanPerThread;
-        uint32_t u[kScanPerThread], sum = 0;
-#pragma unroll
-        for (int j = 0; j < kScanPerThread; j++) {
-            u[j] = 0;
-            if (i0 + j < g.n_chunks) {
-                const uint64_t v = state[i0 + j];
-                bad |= (v & ~kValueMask) == 0;  // a chunk without a size (cannot happen)
-                u[j] = (uint32_t)(v & kValueMask);  // at most 4608 units per chunk
-            }
-            sum += u[j];
-        }
-        const uint32_t incl = (uint32_t)wave_incl_scan((int)sum, lane);  // tile sums stay below 2^26
-        if (lane == 63) s_wave[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, tile = 0;
-#pragma unroll
-        for (int w = 0; w < kScanThreads / 64; w++) {
-            before += w < wave ? s_wave[w] : 0u;
-            tile += s_wave[w];
-        }
-        uint64_t off = carry + before + (incl - sum);
-#pragma unroll
-        for (int j = 0; j < kScanPerThread; j++) {
-            if (i0 + j < g.n_chunks) {
-                bad |= off >= (1ull << 32);  // table offsets are 32-bit (64 GiB of payload)
-                table[2 * (i0 + j)] = (uint32_t)off;
-            }
-            off += u[j];
-        }
-        carry += tile;
-        __syncthreads();  // s_wave is rewritten by the next tile
-    }
-    bad = __syncthreads_or(bad);
-    if (tid == 0) {
-        *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off + 16 * carry;
-        // every chunk is done: a failed prequantization anywhere (NaN/Inf,
-        // overflow) ends the pipeline before the encoder, so the escape-cap
-        // bit of chunks that went on counts only when no such bit is set
-        uint32_t* st = reinterpret_cast<uint32_t*>(out + kOffStatus);
-        uint32_t v = *st;
-        if (v & (kErrNonfinite | kErrEbRange)) v &= ~kErrOutlierCap;
-        if (bad) v |= kErrInternal;
-        *st = v;
-    }
-}
-
-// Final compaction of one chunk by a workgroup of `nthreads` threads: copy
-// the staged payload to the chunk's offset.
-__device__ __forceinline__ void move_chunk(uint8_t* __restrict__ out, const Geom& g, int64_t c, int nthreads)
-{
-    const Scratch* scr = reinterpret_cast<const Scratch*>(out + g.scratch_off);
-    if (scr->pre_status) return;
-    const uint64_t* state = reinterpret_cast<const uint64_t*>(out + g.scratch_off + kScratchStateOff);
-    const uint32_t units = (uint32_t)(state[c] & kValueMask);
-    const uint32_t off = reinterpret_cast<const uint32_t*>(out + g.table_off)[2 * c];
-    const uint4* src = reinterpret_cast<const uint4*>(out + g.stage_off + kStageSlotBytes * c);
-    uint4* dst = reinterpret_cast<uint4*>(out + g.payload_off) + off;
-    for (uint32_t i = threadIdx.x; i < units; i += nthreads) dst[i] = src[i];
+    const Scratch* scr = reinterpret_cast<const Scratch*>(scratch);
+    if (scr->pre_status) return;  // the range pass failed: nothing was compressed
+    uint32_t* st = reinterpret_cast<uint32_t*>(out + kOffStatus);
+    const uint32_t v = *st;
+    if (v & (kErrNonfinite | kErrEbRange)) *st = v & ~kErrOutlierCap;
 }
 
 }  // namespace fz

@@ -68,12 +68,16 @@ constexpr int kScratchGeomOff = 64;
 constexpr int kScratchStateOff = 512;
 // per-block partial value ranges of the REL pass, after the chunk states
 constexpr int kMinmaxBlocks = 2048;
-// staging: chunk c's compacted payload is assembled at stage_off + c * bound
-// by the compression kernel and moved to its place in the stream afterwards
+// staging: each compression workgroup assembles a chunk's compacted payload
+// in a slot of its own (at scr_stage + workgroup * slot bytes in the scratch)
+// and copies it to its place in the stream once the chunk's offset is known;
+// the grid has at most kStageSlots workgroups
 constexpr int64_t kStageSlotBytes = kChunkPayloadBound;
+constexpr int kStageSlots = 768;
 
-// chunk state word (payload size in 16-B units, then its inclusive prefix):
-// flag in the top 2 bits, value below
+// chunk state word: flag in the top 2 bits, value below.  A chunk publishes
+// its payload size in 16-B units (kFlagAgg) once its layers are coded, and
+// its inclusive prefix (kFlagIncl) once its offset is known
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kValueMask = (1ull << 62) - 1;
 
 struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into the scratch)
@@ -83,8 +87,12 @@ struct Geom {  // kept trivially copyable and below 448 bytes (it is copied into
     int64_t grid[3];  // chunks per dimension
     int64_t n_chunks;
     int64_t table_off, flags_off, payload_off;  // = header bytes
-    int64_t scratch_off, minmax_off, stage_off;  // scratch after the worst-case stream
-    int64_t bound;                               // bound includes the scratch and the staging
+    int64_t stream_bound;  // worst-case stream bytes
+    // scratch of one compression: at scratch_off in the output buffer (right
+    // after the worst-case stream), or in a buffer of its own; scr_minmax and
+    // scr_stage are offsets inside it, scr_bytes its size
+    int64_t scratch_off, scr_minmax, scr_stage, scr_bytes;
+    int64_t bound;  // the output buffer with its scratch: scratch_off + scr_bytes
     // fp64 input: the prequantized integers (4 B per value) and the partial
     // value ranges of its REL pass follow the fp32 bound
     int64_t q_off, part64_off, bound64;
@@ -121,11 +129,12 @@ inline bool make_geom(int rank, const uint64_t* dims, Geom* g)
     g->table_off = kHeaderBytes;
     g->flags_off = kHeaderBytes + table;
     g->payload_off = g->flags_off + (int64_t)kFlagBytesPerChunk * g->n_chunks;
-    int64_t worst = g->payload_off + g->n_chunks * kChunkPayloadBound;
-    g->scratch_off = (worst + 255) / 256 * 256;
-    g->minmax_off = g->scratch_off + kScratchStateOff + 8 * g->n_chunks;
-    g->stage_off = (g->minmax_off + 16 * kMinmaxBlocks + 255) / 256 * 256;
-    g->bound = g->stage_off + g->n_chunks * kStageSlotBytes;
+    g->stream_bound = g->payload_off + g->n_chunks * kChunkPayloadBound;
+    g->scratch_off = (g->stream_bound + 255) / 256 * 256;
+    g->scr_minmax = kScratchStateOff + 8 * g->n_chunks;
+    g->scr_stage = (g->scr_minmax + 16 * kMinmaxBlocks + 255) / 256 * 256;
+    g->scr_bytes = g->scr_stage + (g->n_chunks < kStageSlots ? g->n_chunks : kStageSlots) * kStageSlotBytes;
+    g->bound = g->scratch_off + g->scr_bytes;
     const int64_t n = g->n[0] * g->n[1] * g->n[2];  // below 2^46: fewer than 2^31 chunks of 2^15 values
     g->q_off = (g->bound + 255) / 256 * 256;
     g->part64_off = g->q_off + (4 * n + 255) / 256 * 256;

@@ -15,9 +15,11 @@ struct Timing {
     hipEvent_t range_begin, main_begin, main_end, done;
 };
 
-// mode: FZ_EB_ABS, FZ_EB_REL (adds the range pass) or FZ_EB_PWREL
-hipError_t launch_compress(const float* x, uint8_t* out, const Geom& g, const HeaderImage& h, int mode, double eb,
-                           hipStream_t st, const Timing* t = nullptr);
+// mode: FZ_EB_ABS, FZ_EB_REL (adds the range pass) or FZ_EB_PWREL; the
+// compression's scratch (g.scr_bytes) at scr: out + g.scratch_off, or a
+// buffer of its own
+hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, const HeaderImage& h, int mode,
+                           double eb, hipStream_t st, const Timing* t = nullptr);
 // decompression: sb = the bytes readable at s (at least g.payload_off,
 // checked by the caller); no byte past them is read
 hipError_t launch_decompress(const uint8_t* s, uint64_t sb, float* y, const Geom& g, uint32_t* d_err, hipStream_t st);

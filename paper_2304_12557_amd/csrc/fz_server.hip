@@ -57,6 +57,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     void* dev = nullptr;     // [compress area | decompress area]
+    void* stage = nullptr;   // staging slots of the slot's compression batches
     void* pinned = nullptr;  // host staging of the same layout
     std::vector<uint64_t> tickets;
     bool busy = false;
@@ -141,6 +142,7 @@ int launch(fz_server* S, Slot& sl, const std::vector<uint64_t>& tickets)
                                sl.stream) != hipSuccess)
                 return FZ_ERR_HIP;
             plan_bind(&P, dev + kind * kAreaBytes);
+            P.d_stage = sl.stage;
             if (plan_run(&P, sl.stream) != hipSuccess) return FZ_ERR_HIP;
         } else {  // too many chunks for the slot's tables: per-field launches
             for (int i = 0; i < n; i++) {
@@ -246,6 +248,7 @@ void release(fz_server* S)
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.stage) (void)hipFree(sl.stage);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
     }
     S->slots.clear();
@@ -272,7 +275,8 @@ int fz_server_create(uint64_t hbm_budget, int slots, int max_batch, fz_server** 
     for (Slot& sl : S->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc(&sl.dev, 2 * kAreaBytes) != hipSuccess || hipHostMalloc(&sl.pinned, 2 * kAreaBytes, 0) != hipSuccess) {
+            hipMalloc(&sl.dev, 2 * kAreaBytes) != hipSuccess || hipHostMalloc(&sl.pinned, 2 * kAreaBytes, 0) != hipSuccess ||
+            hipMalloc(&sl.stage, stage_bytes(cu_count())) != hipSuccess) {
             release(S);
             delete S;
             return FZ_ERR_HIP;

@@ -248,3 +248,19 @@ def test_global_sizes(shape):
     box = {1: (32768,), 2: (32, 1024), 3: (16, 32, 64)}[len(shape)]
     total = sum(4 * (n // shape[a]) * -(-shape[a] // box[a]) for a in range(len(shape)))
     assert fz.lib().fz_decompress_global_work_bytes(ctypes.byref(fz.dims_of(shape))) == total
+
+@pytest.mark.parametrize("shape", [(512, 512, 512), (100, 500, 500), (1800, 3600), (64, 64, 64), (7,), (1 << 27,)])
+def test_bound_is_stream_plus_scratch(shape):
+    """fz_compress_bound = the worst-case stream, then the scratch with one
+    staging slot per persistent workgroup (at most 768): below 0.7 times the
+    input for the large fields; fz_stream_bound is the stream part alone."""
+    n = int(np.prod(shape))
+    b, sb = fz.compress_bound(shape), fz.stream_bound(shape)
+    assert 0 < sb < b
+    assert sb == O.bound(shape)  # the oracle's own worst-case stream size
+    slot = 16 * 4 * 64 * 16 + 1024 * 8
+    chunks = -(-n // 32768) if len(shape) == 1 else None
+    if n * 4 >= 100 << 20:
+        assert b <= 0.7 * 4 * n, (b, 4 * n)
+    if chunks is not None:
+        assert b - sb >= min(chunks, 768) * slot
