@@ -164,6 +164,25 @@ typedef struct {
 int fz_compress_timed(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out, void *stream,
                       const fz_timing *timing);
 
+/* fz_compress_noalloc -- fz_compress for callers that cannot allocate device
+ * memory (work under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same stream, byte for byte, with the compression's
+ * scratch (chunk tickets and sizes, partial value ranges, staging slots) in a
+ * device array that the library holds, FZ_NOALLOC_SCRATCH_BYTES on each
+ * device it runs on, until the process ends.  The call allocates nothing.
+ *   d_out     : device buffer of out_bytes >= fz_stream_bound(dims) bytes
+ *               (256-byte aligned); on completion it holds the stream
+ * The other arguments and the statuses are those of fz_compress.  A field
+ * whose scratch does not fit the array (more than about 1.3 million chunks,
+ * i.e. about 4.3e10 values) and a d_out smaller than the stream bound return
+ * FZ_ERR_ARG at once.  All calls on one device share its array, and each
+ * call clears what it needs with a kernel on its own stream: calls that
+ * overlap on one device (on different streams, or from several threads)
+ * race and must be serialized by the caller. */
+#define FZ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fz_compress_noalloc(const float *d_in, const fz_dims *dims, double eb, int eb_mode, void *d_out,
+                        size_t out_bytes, void *stream);
+
 /* fz_decompress -- the inverse pipeline (Sec. 4.4 describes it as symmetric
  * to compression).
  *   d_stream     : device pointer to a stream made by fz_compress

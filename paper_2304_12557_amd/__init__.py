@@ -99,6 +99,8 @@ def lib():
         L.fz_header_bytes.restype = ctypes.c_size_t
         L.fz_stream_bound.argtypes = [dp]
         L.fz_stream_bound.restype = ctypes.c_size_t
+        L.fz_compress_noalloc.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.fz_compress_noalloc.restype = ctypes.c_int
         L.fz_compress.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp]
         L.fz_compress.restype = ctypes.c_int
         L.fz_compress_timed.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int, vp, vp, ctypes.POINTER(FzTiming)]
@@ -165,7 +167,7 @@ def lib():
     return _LIB
 
 
-SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_stream_bound", "fz_compress", "fz_compress_timed", "fz_decompress", "fz_stream_info", "fz_strerror",
+SYMBOLS = ["fz_compress_bound", "fz_header_bytes", "fz_stream_bound", "fz_compress_noalloc", "fz_compress", "fz_compress_timed", "fz_decompress", "fz_stream_info", "fz_strerror",
            "fz_batch_create_compress", "fz_batch_create_decompress", "fz_batch_run", "fz_batch_tune",
            "fz_batch_destroy", "fz_server_create", "fz_server_submit", "fz_server_wait", "fz_server_poll",
            "fz_server_stats", "fz_server_reset_stats", "fz_server_destroy", "fz_quality_work_bytes", "fz_quality",
@@ -283,6 +285,28 @@ def compress(x, eb, mode="rel", out=None, stream=None, global_lorenzo=False, eve
             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     if rc:
         raise FzError(rc, "fz_compress")
+    return out
+
+
+def compress_noalloc(x, eb, mode="rel", out=None, stream=None):
+    """fz_compress_noalloc: compress a float32 CUDA tensor with the
+    library's own scratch array; ``out`` (uint8, 256-byte aligned) needs only
+    ``stream_bound`` bytes.  The call allocates nothing when ``out`` is given.
+    Asynchronous on ``stream``; calls that overlap on one device race."""
+    import torch
+
+    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    dims = dims_of(x.shape)
+    need = stream_bound(x.shape)
+    if out is None:
+        out = torch.empty(need, dtype=torch.uint8, device=x.device)
+    else:
+        _check_buffer(out, "out", (torch.uint8,), 256, need)
+    rc = lib().fz_compress_noalloc(ctypes.c_void_p(x.data_ptr()), ctypes.byref(dims), float(eb), _mode(mode),
+                                   ctypes.c_void_p(out.data_ptr()), _nbytes(out), _stream_ptr(stream))
+    if rc:
+        raise FzError(rc, "fz_compress_noalloc")
     return out
 
 

@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["fz_api.hip", "fz_compress.hip", "fz_decompress.hip", "fz_batch.hip", "fz_server.hip", "fz_quality.hip", "fz_ablation.hip", "fz_f64.hip", "fz_global.hip"]
+SRC = ["fz_api.hip", "fz_compress.hip", "fz_decompress.hip", "fz_batch.hip", "fz_server.hip", "fz_quality.hip", "fz_ablation.hip", "fz_f64.hip", "fz_global.hip", "fz_static.hip"]
 LIB = os.path.join(HERE, "libfzmi.so")
 ARCH = os.environ.get("FZ_OFFLOAD_ARCH", "gfx950")
 

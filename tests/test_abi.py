@@ -264,3 +264,19 @@ def test_bound_is_stream_plus_scratch(shape):
         assert b <= 0.7 * 4 * n, (b, 4 * n)
     if chunks is not None:
         assert b - sb >= min(chunks, 768) * slot
+
+
+def test_noalloc_argument_checks_on_the_host():
+    """fz_compress_noalloc rejects, before touching any device, a missing
+    pointer, an output smaller than the stream bound and a field whose
+    scratch does not fit the library's array (FZ_ERR_ARG = 1)."""
+    L = fz.lib()
+    p = ctypes.c_void_p(256)  # never dereferenced: every call below fails its checks first
+    d = fz.dims_of((64, 64, 64))
+    sb = fz.stream_bound((64, 64, 64))
+    assert L.fz_compress_noalloc(None, ctypes.byref(d), 1e-3, 1, p, sb, None) == 1
+    assert L.fz_compress_noalloc(p, ctypes.byref(d), 1e-3, 1, None, sb, None) == 1
+    assert L.fz_compress_noalloc(p, ctypes.byref(d), 1e-3, 1, p, sb - 1, None) == 1
+    big = fz.dims_of((1 << 36,))  # 2^21 chunks
+    assert L.fz_compress_noalloc(p, ctypes.byref(big), 1e-3, 1, p, 1 << 62, None) == 1
+
