@@ -35,6 +35,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="lognormal3d",
+                   choices=("lognormal3d", "sine3d", "climate2d", "hurricane3d"),
+                   help="the field of the timed steps: the 512^3 cosmology-like lognormal field (default, edge --n), "
+                        "or one of the other paper-shaped fields (64^3 sine modes, the 1800x3600 climate-like and "
+                        "the 100x500x500 hurricane-like field) for a trace of their kernels alone")
     p.add_argument("--n", type=int, default=512, help="edge of the cubic lognormal field")
     p.add_argument("--eb", type=float, default=1e-3)
     p.add_argument("--seed", type=int, default=300)
@@ -783,7 +788,14 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    x = synth.lognormal3d(seed=a.seed, n=a.n)
+    if a.workload == "lognormal3d":
+        x = synth.lognormal3d(seed=a.seed, n=a.n)
+        wname = "lognormal3d %d^3 fp32 (cosmology-like)" % a.n
+    else:
+        x = getattr(synth, a.workload)()
+        wname = {"sine3d": "sine3d 64x64x64 fp32 (8 sine modes + noise)",
+                 "climate2d": "climate2d 1800x3600 fp32 (16 modes, 20 % exact zeros)",
+                 "hurricane3d": "hurricane3d 100x500x500 fp32 (12 modes + vortex)"}[a.workload]
     shape = x.shape
     N = x.size
     in_bytes = 4 * N
@@ -857,8 +869,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "lognormal3d %d^3 fp32 (cosmology-like), REL eb %g, compress + decompress"
-                               % (a.n, a.eb), "dims": list(shape), "eb": a.eb, "eb_mode": "rel"},
+        "config": {"workload": "%s, REL eb %g, compress + decompress" % (wname, a.eb), "dims": list(shape),
+                   "eb": a.eb, "eb_mode": "rel"},
         "timing_note": "each compression and decompression is preceded, outside its events, by a 1 GiB read that "
                        "evicts the caches (%.3f ms, inside ms_per_step twice per step)" % float(np.mean(t_ev)),
         "compress_GBps": round(in_bytes / 1e9 / (tc * 1e-3), 2),
@@ -887,7 +899,7 @@ def main():
         out["pointwise_relative"] = pointwise_relative(xt, shape, stream, a.steps)
         out["fp64_input"] = fp64_input(xt, shape, a.eb, stream, a.steps)
         hur = torch.from_numpy(synth.hurricane3d()).to(dev)
-        out["global_predictor"] = global_predictor([("lognormal3d %d^3" % a.n, xt, a.eb),
+        out["global_predictor"] = global_predictor([(wname.split(" fp32")[0], xt, a.eb),
                                                     ("hurricane3d 100x500x500", hur, 1e-3)], stream, a.steps)
         del hur
     if not a.no_ablation:

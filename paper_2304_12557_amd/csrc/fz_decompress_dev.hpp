@@ -27,27 +27,33 @@ namespace fz {
 __device__ __forceinline__ uint32_t check_header(const uint8_t* __restrict__ s, const Geom& g, int rank, int dtype,
                                                  int predictor, uint64_t s_bytes)
 {
-    const uint32_t w0 = *reinterpret_cast<const uint32_t*>(s + kOffMagic);
-    const uint32_t w1 = *reinterpret_cast<const uint32_t*>(s + kOffVersion);
-    if (w0 != kMagic) return 6;                                     // FZ_ERR_STREAM
-    if (w1 != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16))) return 7;  // FZ_ERR_VERSION
-    if (*reinterpret_cast<const uint32_t*>(s + kOffStatus) != 0u) return 8;    // FZ_ERR_STATUS
-    if (s[kOffDtype] != dtype || s[kOffRank] != rank || s[kOffEbMode] > (dtype ? 1 : 2)) return 6;
-    if (s[kOffPredictor] != predictor) return 6;
+    // the whole header at once, as 32-bit words, and every check on them
+    // without an early exit: the loads are uniform and issued together (one
+    // wait), where byte loads behind branches would each wait in turn
+    const uint32_t* hw = reinterpret_cast<const uint32_t*>(s);
+    uint32_t w[kHeaderBytes / 4];
+#pragma unroll
+    for (int i = 0; i < kHeaderBytes / 4; i++) w[i] = hw[i];
+    auto byte_at = [&](int off) { return (w[off / 4] >> (8 * (off % 4))) & 0xFFu; };
+    auto u64_at = [&](int off) { return (uint64_t)w[off / 4] | ((uint64_t)w[off / 4 + 1] << 32); };
+    bool bad = byte_at(kOffDtype) != (uint32_t)dtype || byte_at(kOffRank) != (uint32_t)rank ||
+               byte_at(kOffEbMode) > (dtype ? 1u : 2u) || byte_at(kOffPredictor) != (uint32_t)predictor;
     if (dtype) {  // 2 eb as a normal, finite double
-        const double e2 = *reinterpret_cast<const double*>(s + kOffEbx2F64);
-        if (!(e2 >= 2.2250738585072014e-308 && e2 <= 1.7976931348623157e308)) return 6;
+        const double e2 = __longlong_as_double((long long)u64_at(kOffEbx2F64));
+        bad |= !(e2 >= 2.2250738585072014e-308 && e2 <= 1.7976931348623157e308);
     }
-    if (s[kOffEbMode] == 2) {  // the point-wise mode's step: an integer in [2, 2^24)
-        const float st = *reinterpret_cast<const float*>(s + kOffEbx2);
-        if (!(st >= 2.0f && st < 16777216.0f) || st != __builtin_floorf(st)) return 6;
-    }
-    for (int i = 0; i < 3; i++)
-        if (reinterpret_cast<const uint64_t*>(s + kOffDims)[i] != (uint64_t)g.n[i]) return 6;
-    if (*reinterpret_cast<const uint32_t*>(s + kOffNChunks) != (uint32_t)g.n_chunks) return 6;
-    const uint64_t total = *reinterpret_cast<const uint64_t*>(s + kOffTotal);
-    if (total < (uint64_t)g.payload_off || ((total - g.payload_off) & 15) != 0 || total > s_bytes) return 6;
-    return 0;
+    const float st = __uint_as_float(w[kOffEbx2 / 4]);  // the point-wise mode's step: an integer in [2, 2^24)
+    bad |= byte_at(kOffEbMode) == 2 && (!(st >= 2.0f && st < 16777216.0f) || st != __builtin_floorf(st));
+#pragma unroll
+    for (int i = 0; i < 3; i++) bad |= u64_at(kOffDims + 8 * i) != (uint64_t)g.n[i];
+    bad |= w[kOffNChunks / 4] != (uint32_t)g.n_chunks;
+    const uint64_t total = u64_at(kOffTotal);
+    bad |= total < (uint64_t)g.payload_off || ((total - g.payload_off) & 15) != 0 || total > s_bytes;
+    // the codes in the order of their precedence
+    return w[kOffMagic / 4] != kMagic ? 6u                                                          // FZ_ERR_STREAM
+         : w[kOffVersion / 4] != ((uint32_t)kVersion | ((uint32_t)kHeaderBytes << 16)) ? 7u  // FZ_ERR_VERSION
+         : w[kOffStatus / 4] != 0u ? 8u                                                      // FZ_ERR_STATUS
+         : bad ? 6u : 0u;
 }
 
 // Sign-magnitude decode (Sec. 3.2).  The transpose ran with plane 15 (the
@@ -274,6 +280,18 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     // past its nonzero bricks return 0, never another chunk's bytes)
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint4*>(pay + off), (short)0, (int)(16u * nnz), kBufferFlags);
+    {
+        // The bricks are read a few words per step over the chunk's 16 steps:
+        // touch all their lines now (64 lines per instruction), so that the
+        // later steps' loads find them in the caches instead of HBM.  The
+        // words land in 256 bytes of LDS that nothing reads: a load into LDS
+        // holds no register and nothing waits for it (the first step's wait
+        // for its own words, issued after these, covers them in order).
+        __shared__ uint32_t touch_dump[64];
+        for (uint32_t o = 0; o < 16u * nnz; o += 8192u)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)touch_dump, 4,
+                                                     o + 128u * (uint32_t)lane, 0, 0, 0);
+    }
 
     // per-step brick words: plane b of this lane's brick holds word t of
     // step 4k + t at byte voff[b] + 4t of the chunk's payload.  A zero brick
@@ -560,7 +578,9 @@ __device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__
         // (dequantized after the carries, in any mode)
         decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
     } else {
-        if (s[kOffEbMode] == 2) decompress_chunk<RANK, VEC4, true, T>(s, s_bytes, y, g, d_err, c, lane, tile);
+        // the mode byte from its (uniform, scalar-loaded) header word
+        const uint32_t mode = (reinterpret_cast<const uint32_t*>(s)[kOffEbMode / 4] >> (8 * (kOffEbMode % 4))) & 0xFFu;
+        if (mode == 2) decompress_chunk<RANK, VEC4, true, T>(s, s_bytes, y, g, d_err, c, lane, tile);
         else decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
     }
 }
