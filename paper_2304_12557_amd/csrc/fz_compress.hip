@@ -8,8 +8,9 @@
 // staged in its workgroup's slot and placed one chunk later, when the sizes
 // of the chunks before it are almost always published, so the look-back
 // rarely waits; then the slot, still in the cache, is copied to the chunk's
-// offset.  k_finish settles the status word.  REL mode runs k_minmax +
-// k_params first (the value range).
+// offset.  k_finish settles the status word.  REL mode runs k_minmax first
+// (the value range, plus k_init's work), and k_compress folds the range into
+// the eb parameters itself.
 #include <hip/hip_runtime.h>
 
 #include "fz.h"
@@ -18,16 +19,28 @@
 
 namespace fz {
 
+// rel_eb > 0: a REL compression whose range pass (k_minmax) left nparts
+// partial ranges; every workgroup folds them itself into the eb parameters
+// (the same bits everywhere) and workgroup 0 writes them to the header, so
+// no separate launch sits between the range pass and this kernel.
 template <int RANK, bool VEC4, int QM>
 __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x, uint8_t* __restrict__ out,
-                                                     uint8_t* __restrict__ scratch, Geom g)
+                                                     uint8_t* __restrict__ scratch, Geom g, double rel_eb, int nparts)
 {
     __shared__ CompressLds S;
     Scratch* scr = reinterpret_cast<Scratch*>(scratch);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: keep it scalar
-    if (scr->pre_status) return;  // set before this launch: uniform across the grid
-    const Quant inv = quant_of(out);
+    Quant inv;
+    if (rel_eb > 0.0) {
+        const RelParams r = fold_params(scratch, g, rel_eb, nparts);
+        if (blockIdx.x == 0 && threadIdx.x == 0) write_params(out, scratch, g, r);
+        if (r.status) return;  // the same in every workgroup
+        inv = Quant{r.inv, 0u, 0u};
+    } else {
+        if (scr->pre_status) return;  // set before this launch: uniform across the grid
+        inv = quant_of(out);
+    }
     uint64_t* state = reinterpret_cast<uint64_t*>(scratch + kScratchStateOff);
     uint8_t* slot = scratch + g.scr_stage + kStageSlotBytes * (int64_t)blockIdx.x;
 
@@ -94,9 +107,13 @@ __global__ __launch_bounds__(256) void k_init(uint8_t* __restrict__ out, uint8_t
     init_field(out, scratch, g, h, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ scratch,
-                                                Geom g)
+// the range pass; with `init` it also does k_init's work (a REL compression
+// starts with it)
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, uint8_t* __restrict__ out,
+                                                uint8_t* __restrict__ scratch, Geom g, HeaderImage h, int init)
 {
+    if (init)
+        init_field(out, scratch, g, h, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
     minmax_block(x, n, scratch, g, blockIdx.x, gridDim.x);
 }
 
@@ -118,7 +135,7 @@ static hipError_t mark(hipEvent_t e, hipStream_t st) { return e ? hipEventRecord
 
 template <int RANK, bool VEC4, int QM>
 static hipError_t launch_rank(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, hipStream_t st,
-                              const Timing* t = nullptr)
+                              const Timing* t = nullptr, double rel_eb = 0.0, int nparts = 0)
 {
     // persistent grid: as many workgroups as stay resident, at most one per chunk
     int dev = 0, cus = 0, per_cu = 0;
@@ -132,7 +149,8 @@ static hipError_t launch_rank(const float* x, uint8_t* out, uint8_t* scr, const 
     if (grid > g.n_chunks) grid = g.n_chunks;
     hipError_t e;
     if (t && (e = mark(t->main_begin, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, scr, g);
+    hipLaunchKernelGGL((k_compress<RANK, VEC4, QM>), dim3((unsigned)grid), dim3(256), 0, st, x, out, scr, g, rel_eb,
+                       nparts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t && (e = mark(t->main_end, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, out, scr);
@@ -174,12 +192,12 @@ hipError_t launch_compress_f64(const double* x, uint8_t* out, const Geom& g, con
     return launch_main_int(out, g, st);
 }
 
-// the value range and the eb parameters of the relative bound
+// the value range and the eb parameters of the relative bound (after k_init)
 static hipError_t launch_range(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, double eb, hipStream_t st)
 {
     const int64_t n = g.n[0] * g.n[1] * g.n[2];
     const int64_t blocks = minmax_blocks(n);
-    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, scr, g);
+    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, scr, g, HeaderImage{}, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, st, out, scr, g, eb, (int)blocks);
@@ -200,10 +218,23 @@ hipError_t launch_compress_global(const float* x, uint8_t* out, const Geom& g, c
 hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, const HeaderImage& h, int mode,
                            double eb, hipStream_t st, const Timing* t)
 {
-    hipError_t e = launch_init(out, scr, g, h, st);
-    if (e != hipSuccess) return e;
-    if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
-    if (mode == FZ_EB_REL && (e = launch_range(x, out, scr, g, eb, st)) != hipSuccess) return e;
+    // REL: the range pass also initializes (the header image, the scratch), and
+    // the compression kernel folds the range itself: 3 launches with k_finish
+    hipError_t e;
+    double rel_eb = 0.0;
+    int nparts = 0;
+    if (mode == FZ_EB_REL) {
+        if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
+        const int64_t n = g.n[0] * g.n[1] * g.n[2];
+        const int64_t blocks = minmax_blocks(n);
+        hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, st, x, n, out, scr, g, h, 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        rel_eb = eb;
+        nparts = (int)blocks;
+    } else {
+        if ((e = launch_init(out, scr, g, h, st)) != hipSuccess) return e;
+        if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
+    }
     const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     if (mode == FZ_EB_PWREL) {
         switch (g.rank * 2 + (vec4 ? 1 : 0)) {
@@ -216,12 +247,12 @@ hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geo
         }
     }
     switch (g.rank * 2 + (vec4 ? 1 : 0)) {
-        case 7: return launch_rank<3, true, kQuantGrid>(x, out, scr, g, st, t);
-        case 6: return launch_rank<3, false, kQuantGrid>(x, out, scr, g, st, t);
-        case 5: return launch_rank<2, true, kQuantGrid>(x, out, scr, g, st, t);
-        case 4: return launch_rank<2, false, kQuantGrid>(x, out, scr, g, st, t);
-        case 3: return launch_rank<1, true, kQuantGrid>(x, out, scr, g, st, t);
-        default: return launch_rank<1, false, kQuantGrid>(x, out, scr, g, st, t);
+        case 7: return launch_rank<3, true, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
+        case 6: return launch_rank<3, false, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
+        case 5: return launch_rank<2, true, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
+        case 4: return launch_rank<2, false, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
+        case 3: return launch_rank<1, true, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
+        default: return launch_rank<1, false, kQuantGrid>(x, out, scr, g, st, t, rel_eb, nparts);
     }
 }
 

@@ -908,15 +908,21 @@ __device__ __forceinline__ void minmax_block(const float* __restrict__ x, int64_
     }
 }
 
-// Fold the partial ranges of one field and derive the eb parameters (one
-// block of 256 threads): eb_abs = eb * (vmax - vmin) in double (a constant
-// field uses eb * |vmax|, or eb if that is 0), ebx2 = fp32(2 eb_abs),
+// The eb parameters of a REL compression, from the folded value range.
+struct RelParams {
+    uint32_t status;          // 0, kErrNonfinite or kErrEbRange
+    float ebx2, inv, vmin, vmax;
+};
+
+// Fold the partial ranges of one field and derive the eb parameters, by one
+// block of blockDim.x threads (a multiple of 64, at most 1024); every thread
+// gets the result.  eb_abs = eb * (vmax - vmin) in double (a constant field
+// uses eb * |vmax|, or eb if that is 0), ebx2 = fp32(2 eb_abs),
 // inv = fp32(1 / (double)ebx2).
-__device__ __forceinline__ void params_field(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, const Geom& g,
-                                             double eb, int nparts)
+__device__ __forceinline__ RelParams fold_params(const uint8_t* __restrict__ scratch, const Geom& g, double eb,
+                                                 int nparts)
 {
-    __shared__ uint32_t s_red[3][4];
-    Scratch* scr = reinterpret_cast<Scratch*>(scratch);
+    __shared__ uint32_t s_red[3][16];
     const uint32_t* part = reinterpret_cast<const uint32_t*>(scratch + g.scr_minmax);
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
@@ -930,41 +936,60 @@ __device__ __forceinline__ void params_field(uint8_t* __restrict__ out, uint8_t*
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, sh));
         bad |= (uint32_t)__shfl_xor((int)bad, sh);
     }
-    const int w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if ((threadIdx.x & 63) == 0) { s_red[0][w] = lo; s_red[1][w] = hi; s_red[2][w] = bad; }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    lo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
-    hi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
-    bad = s_red[2][0] | s_red[2][1] | s_red[2][2] | s_red[2][3];
-    uint32_t status = 0;
-    float e2 = 0.0f, iv = 0.0f, flo = 0.0f, fhi = 0.0f;
+    lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
+    for (int i = 0; i < nw; i++) {
+        lo = min(lo, s_red[0][i]);
+        hi = max(hi, s_red[1][i]);
+        bad |= s_red[2][i];
+    }
+    __syncthreads();  // s_red may be reused by the caller's next fold
+    RelParams r{0u, 0.0f, 0.0f, 0.0f, 0.0f};
     if (bad) {
-        status = kErrNonfinite;
+        r.status = kErrNonfinite;
     } else {
-        flo = key_float(lo);
-        fhi = key_float(hi);
-        const double range = (double)fhi - (double)flo;
+        r.vmin = key_float(lo);
+        r.vmax = key_float(hi);
+        const double range = (double)r.vmax - (double)r.vmin;
         double eb_abs;
         if (range > 0.0) eb_abs = eb * range;
         else {
-            const double a = __builtin_fabs((double)fhi);
+            const double a = __builtin_fabs((double)r.vmax);
             eb_abs = eb * (a > 0.0 ? a : 1.0);
         }
-        e2 = (float)(2.0 * eb_abs);
-        iv = (float)(1.0 / (double)e2);
-        if (!(e2 >= 1.17549435e-38f) || !__builtin_isfinite(e2) || !__builtin_isfinite(iv) || !(iv > 0.0f))
-            status = kErrEbRange;
+        r.ebx2 = (float)(2.0 * eb_abs);
+        r.inv = (float)(1.0 / (double)r.ebx2);
+        if (!(r.ebx2 >= 1.17549435e-38f) || !__builtin_isfinite(r.ebx2) || !__builtin_isfinite(r.inv) || !(r.inv > 0.0f))
+            r.status = kErrEbRange;
     }
-    *reinterpret_cast<float*>(out + kOffEbx2) = e2;
-    *reinterpret_cast<float*>(out + kOffInv) = iv;
-    *reinterpret_cast<float*>(out + kOffVmin) = flo;
-    *reinterpret_cast<float*>(out + kOffVmax) = fhi;
-    if (status) {
-        *reinterpret_cast<uint32_t*>(out + kOffStatus) = status;
+    return r;
+}
+
+// The header's eb fields (and, on a failed range, its status and total) and
+// the scratch's pre_status, by one thread.
+__device__ __forceinline__ void write_params(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, const Geom& g,
+                                             const RelParams& r)
+{
+    *reinterpret_cast<float*>(out + kOffEbx2) = r.ebx2;
+    *reinterpret_cast<float*>(out + kOffInv) = r.inv;
+    *reinterpret_cast<float*>(out + kOffVmin) = r.vmin;
+    *reinterpret_cast<float*>(out + kOffVmax) = r.vmax;
+    if (r.status) {
+        *reinterpret_cast<uint32_t*>(out + kOffStatus) = r.status;
         *reinterpret_cast<uint64_t*>(out + kOffTotal) = (uint64_t)g.payload_off;
     }
-    scr->pre_status = status;
+    reinterpret_cast<Scratch*>(scratch)->pre_status = r.status;
+}
+
+// The eb parameters by a block of its own (the batch layer, the field-global
+// predictor): fold, then thread 0 writes them.
+__device__ __forceinline__ void params_field(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, const Geom& g,
+                                             double eb, int nparts)
+{
+    const RelParams r = fold_params(scratch, g, eb, nparts);
+    if (threadIdx.x == 0) write_params(out, scratch, g, r);
 }
 
 // End of one field's compression, after every chunk is placed (a launch of
