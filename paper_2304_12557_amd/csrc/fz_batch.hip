@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         const bool skip = reinterpret_cast<const Scratch*>(scr)->pre_status != 0;
         const Quant inv = quant_of(J.out);
         const Lane l = lane_geo<RANK>(g, c, lane);
-        if (!skip && !l.edge && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
+        if (!skip && !loaded) prefetch<RANK, VEC4>(J.x, g, l, wave, h, v, swept_down<RANK>(wave));
         uint32_t tk;  // the next ticket, taken early by thread 0 (its return has the layer to arrive)
         if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
         uint64_t F[16], myflag = 0;
@@ -118,10 +118,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
         loaded = false;
         if (jn == j && !skip) {  // same field: start the next chunk's loads now
             const Lane ln = lane_geo<RANK>(g, tn - J.chunk0, lane);
-            if (!ln.edge) {
-                prefetch<RANK, VEC4>(J.x, g, ln, wave, lane, h, v, swept_down<RANK>(wave));
-                loaded = true;
-            }
+            prefetch<RANK, VEC4>(J.x, g, ln, wave, h, v, swept_down<RANK>(wave));
+            loaded = true;
         }
         if (!loaded) {  // defined on every path, so that no value of this chunk stays live into the next
 #pragma unroll

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     if (c >= g.n_chunks) return;
     float h[32], v[32];
     Lane l = lane_geo<RANK>(g, c, lane);
-    if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
+    prefetch<RANK, VEC4>(x, g, l, wave, h, v, swept_down<RANK>(wave));
     int64_t pend = -1;  // the chunk staged in this workgroup's slot, not yet placed
     uint32_t pend_units = 0;
 
@@ -71,10 +71,9 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
         if (cn < g.n_chunks) {  // start loading the next chunk while this one is placed
             l = lane_geo<RANK>(g, cn, lane);
-            if (!l.edge) prefetch<RANK, VEC4>(x, g, l, wave, lane, h, v, swept_down<RANK>(wave));
-        }
-        if (cn >= g.n_chunks || l.edge) {  // defined on every path: otherwise the values of this chunk's
-                                            // last step stay live across the placement and are spilled
+            prefetch<RANK, VEC4>(x, g, l, wave, h, v, swept_down<RANK>(wave));
+        } else {  // defined on every path: otherwise the values of this chunk's
+                  // last step stay live across the placement and are spilled
 #pragma unroll
             for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
         }

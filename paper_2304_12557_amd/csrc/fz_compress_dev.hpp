@@ -100,14 +100,22 @@ __device__ __forceinline__ void prequant32(const float (&v)[32], const Quant& z,
 }
 
 // ------------------------------------------------------------------ loaders
-// Interior loads go through a buffer resource whose base is the (uniform)
-// first value of the step: a lane keeps one 32-bit byte offset for the whole
-// chunk and the row offsets are uniform, so no 64-bit per-lane address is
-// held in registers.
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const float* base)
+// Loads go through a buffer resource whose base is the (uniform) first value
+// of the step: a lane keeps one 32-bit byte offset for the whole chunk and
+// the row offsets are uniform, so no 64-bit per-lane address is held in
+// registers.  The resource's range ends at the field's last value, so a load
+// past it returns 0 without touching memory.  A chunk cut by the field's edge
+// is loaded exactly like an interior one: its cells outside the field read 0
+// (past the end) or values of other chunks (the rest of a row, the next
+// rows), and their deltas are set to 0 afterwards (mask_outside), while the
+// delta of a cell inside the field only looks at cells inside it.
+// (on = false: a range of 0, every load returns 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const float* __restrict__ x, const Geom& g,
+                                                           const float* base, bool on = true)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, -1, kBufferFlags);
+    const int64_t left = 4 * (g.n[0] * g.n[1] * g.n[2] - (base - x));  // uniform
+    const int range = !on || left <= 0 ? 0 : left >= 0xFFFFFFFFll ? -1 : (int)(uint32_t)left;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, range, kBufferFlags);
 }
 
 // NT: a nontemporal (streaming) load, for values this chunk reads only once
@@ -135,7 +143,6 @@ struct Lane {
     int L;
     bool edge;
     uint32_t off;  // lane offset of its first value inside a step
-    int ev, eh;    // 3-D: valid rows / columns of the patch; 2-D: columns
 };
 
 template <int RANK>
@@ -143,6 +150,14 @@ __device__ __forceinline__ Lane lane_geo(const Geom& g, int64_t c, int lane)
 {
     Lane l;
     chunk_box(g, c, l.org, l.ext);
+    // the box is the same on every lane, but its divisions run on the vector
+    // unit: copied to scalar registers, so that the loads' row offsets and
+    // resources built from it stay scalar
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        l.org[i] = uniform64(l.org[i]);
+        l.ext[i] = uniform64(l.ext[i]);
+    }
     l.L = layers_of(RANK, l.ext[0]);
     l.edge = false;
 #pragma unroll
@@ -150,16 +165,10 @@ __device__ __forceinline__ Lane lane_geo(const Geom& g, int64_t c, int lane)
     if (RANK == 3) {
         const int py = lane & 7, px = lane >> 3;
         l.off = (uint32_t)(4 * py * g.n[2] + 8 * px);
-        l.ev = clampi(l.ext[1] - 4 * py, 0, 4);
-        l.eh = clampi(l.ext[2] - 8 * px, 0, 8);
     } else if (RANK == 2) {
         l.off = (uint32_t)(16 * lane);
-        l.ev = 2;
-        l.eh = clampi(l.ext[1] - 16 * lane, 0, 16);
     } else {
         l.off = (uint32_t)(kPatchCodes * lane);
-        l.ev = 1;
-        l.eh = 32;
     }
     return l;
 }
@@ -173,114 +182,77 @@ __device__ __forceinline__ const float* step_base(const float* __restrict__ x, c
     return x + l.org[0] + (int64_t)kStepCodes * s;
 }
 
-// load the lane's 32 values of step s (s = 4k-1 is the halo of layer k).
-// In a chunk cut by the field's edge, cells outside the field hold 0 (rows
-// whose 16-byte pieces are whole vectors: through a buffer resource whose
-// range ends at the chunk's last in-field value, with an offset past it for
-// the pieces outside the field) or a clamped in-field value (other rows);
-// either way their deltas are zeroed later (a delta inside the field never
-// looks at a cell outside it).
-// 3-D interior loads are nontemporal except for the top step of a layer
-// (s mod 4 = 3), which the next layer's wave reads again as its halo in the
-// same iteration and must find in the cache (measured: the 512^3 ABS
-// compression 173 -> 166 us).  After unrolling, s mod 4 is a constant.  In
-// 2-D and 1-D a lane's run spans 4 or 8 load instructions per line, and
-// nontemporal loads there measured 6 % and 40 % slower: lines left before
-// the rest of their run was read.
-template <int RANK, bool EDGE, bool VEC4>
-__device__ __forceinline__ void load_step(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s, int lane,
-                                          float (&v)[32])
+// load the lane's 32 values of step s (s = 4k-1 is the halo of layer k),
+// through the step's ranged resource (step_rsrc; on = false: zeros).  NT: 3-D
+// loads nontemporal (streaming).
+template <int RANK, bool VEC4, bool NT>
+__device__ __forceinline__ void load_step_as(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s,
+                                             bool on, float (&v)[32])
 {
     const float* b = step_base<RANK>(x, g, l, s);
+    const __amdgpu_buffer_rsrc_t rs = step_rsrc(x, g, b, on);
     if (RANK == 3) {
         const int64_t nx = g.n[2];
-        if (EDGE && VEC4 && 32 * 4 * nx < 0x80000000ll) {  // uniform; ext[2] is a multiple of 4 here
-            const int py = lane & 7, px = lane >> 3;
-            const uint32_t rows = (uint32_t)l.ext[1], cols = (uint32_t)l.ext[2];
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(b), (short)0, (int)(4u * ((rows - 1) * (uint32_t)nx + cols)), kBufferFlags);
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const uint32_t row = 4u * py + r;
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const uint32_t col = 8u * px + 4u * j;
-                    const uint32_t voff = row < rows && col < cols ? 4u * (row * (uint32_t)nx + col) : 0x80000000u;
-                    const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0u, 0);
-                    v[8 * r + 4 * j] = __uint_as_float(t.x); v[8 * r + 4 * j + 1] = __uint_as_float(t.y);
-                    v[8 * r + 4 * j + 2] = __uint_as_float(t.z); v[8 * r + 4 * j + 3] = __uint_as_float(t.w);
-                }
-            }
-        } else if (EDGE) {
-            const int py = lane & 7, px = lane >> 3;
-            const int ey = (int)l.ext[1] - 1, ex = (int)l.ext[2] - 1;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const float* p = b + (uint32_t)min(4 * py + r, ey) * (uint32_t)nx;
-#pragma unroll
-                for (int c = 0; c < 8; c++) v[8 * r + c] = p[min(8 * px + c, ex)];
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
-            if ((s & 3) == 3) {
-#pragma unroll
-                for (int r = 0; r < 4; r++) load_run<8, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 8 * r);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; r++) load_run<8, VEC4, true>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 8 * r);
-            }
-        }
+        for (int r = 0; r < 4; r++) load_run<8, VEC4, NT>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 8 * r);
     } else if (RANK == 2) {
         const int64_t nx = g.n[1];
-        if (EDGE && VEC4 && 2 * 4 * nx < 0x80000000ll) {  // uniform; ext[1] is a multiple of 4 here
-            const uint32_t rows = (uint32_t)min((int64_t)2, l.ext[0] - 2 * s), cols = (uint32_t)l.ext[1];
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(b), (short)0, (int)(4u * ((rows - 1) * (uint32_t)nx + cols)), kBufferFlags);
 #pragma unroll
-            for (int r = 0; r < 2; r++) {
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const uint32_t col = 16u * lane + 4u * j;
-                    const uint32_t voff = (uint32_t)r < rows && col < cols ? 4u * ((uint32_t)r * (uint32_t)nx + col)
-                                                                            : 0x80000000u;
-                    const fz_u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0u, 0);
-                    v[16 * r + 4 * j] = __uint_as_float(t.x); v[16 * r + 4 * j + 1] = __uint_as_float(t.y);
-                    v[16 * r + 4 * j + 2] = __uint_as_float(t.z); v[16 * r + 4 * j + 3] = __uint_as_float(t.w);
-                }
-            }
-        } else if (EDGE) {
-            const int ex = (int)l.ext[1] - 1;
-            const int64_t last = l.ext[0] - 1 - 2 * s;  // last field row relative to the step
-#pragma unroll
-            for (int r = 0; r < 2; r++) {
-                const float* p = b + (r < last ? r : last) * nx;
-#pragma unroll
-                for (int c = 0; c < 16; c++) v[16 * r + c] = p[min(16 * lane + c, ex)];
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rs = step_rsrc(b);
-#pragma unroll
-            for (int r = 0; r < 2; r++) load_run<16, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 16 * r);
-        }
+        for (int r = 0; r < 2; r++) load_run<16, VEC4>(rs, 4u * l.off, (uint32_t)(4 * r * nx), v + 16 * r);
     } else {
-        if (EDGE) {
-            const int64_t last = l.ext[0] - 1 - (int64_t)kStepCodes * s;
-#pragma unroll
-            for (int m = 0; m < 32; m++) {
-                const int64_t i = (int64_t)l.off + m;
-                v[m] = b[i < last ? i : last];
-            }
-        } else {
-            load_run<32, VEC4>(step_rsrc(b), 4u * l.off, 0u, v);
-        }
+        load_run<32, VEC4>(rs, 4u * l.off, 0u, v);
     }
+}
+
+// 3-D loads are nontemporal except for the top step of a layer (s mod 4 =
+// 3), which the next layer's wave reads again as its halo in the same
+// iteration and must find in the cache (measured: the 512^3 ABS compression
+// 173 -> 166 us).  After unrolling, s mod 4 is a constant.  In 2-D and 1-D a
+// lane's run spans 4 or 8 load instructions per line, and nontemporal loads
+// there measured 6 % and 40 % slower: lines left before the rest of their run
+// was read.
+template <int RANK, bool VEC4>
+__device__ __forceinline__ void load_step(const float* __restrict__ x, const Geom& g, const Lane& l, int64_t s,
+                                          float (&v)[32])
+{
+    if ((s & 3) == 3) load_step_as<RANK, VEC4, false>(x, g, l, s, true, v);
+    else load_step_as<RANK, VEC4, RANK == 3>(x, g, l, s, true, v);
+}
+
+// The lane's cells of step s inside the field, one bit per value of d (all
+// set in a chunk not cut by the field's edge): 3-D, its rows r < ev and
+// columns c < eh of a plane inside the field; 2-D, its columns c < eh of the
+// step's rows inside the field; 1-D, its values inside the field.
+template <int RANK>
+__device__ __forceinline__ uint32_t keep_bits(const Lane& l, int64_t s, int lane)
+{
+    if (RANK == 3) {
+        const int ev = clampi(l.ext[1] - 4 * (lane & 7), 0, 4), eh = clampi(l.ext[2] - 8 * (lane >> 3), 0, 8);
+        const uint32_t cells = (uint32_t)((1ull << (8 * ev)) - 1ull) & (((1u << eh) - 1u) * 0x01010101u);
+        return s < l.ext[0] ? cells : 0u;
+    } else if (RANK == 2) {
+        const uint32_t cols = (uint32_t)((1ull << clampi(l.ext[1] - 16 * lane, 0, 16)) - 1ull);
+        return (2 * s < l.ext[0] ? cols : 0u) | (2 * s + 1 < l.ext[0] ? cols << 16 : 0u);
+    } else {
+        const int valid = clampi(l.ext[0] - ((int64_t)kStepCodes * s + l.off), 0, 32);
+        return (uint32_t)((1ull << valid) - 1ull);
+    }
+}
+
+// Deltas of the cells of step s outside the field set to 0 (the logging
+// pass, which must not log an escape for such a cell).
+template <int RANK>
+__device__ __forceinline__ void mask_outside(int (&d)[32], const Lane& l, int64_t s, int lane)
+{
+    const uint32_t keep = keep_bits<RANK>(l, s, lane);
+#pragma unroll
+    for (int i = 0; i < 32; i++) d[i] &= __builtin_amdgcn_sbfe((int)keep, (uint32_t)i, 1u);
 }
 
 // ------------------------------------------------------------- one layer
 // In-plane part of the Lorenzo difference, after the difference along the
 // sweep dimension.  3-D: `a` is a plane difference; Dy then Dx give d.
-template <bool EDGE>
-__device__ __forceinline__ void inplane3(const int (&a)[32], int (&d)[32], const Lane& l, int lane)
+__device__ __forceinline__ void inplane3(const int (&a)[32], int (&d)[32], int lane)
 {
     const int py = lane & 7, px = lane >> 3;
     int b[32];
@@ -300,19 +272,11 @@ __device__ __forceinline__ void inplane3(const int (&a)[32], int (&d)[32], const
 #pragma unroll
         for (int c = 1; c < 8; c++) d[8 * r + c] = b[8 * r + c] - b[8 * r + c - 1];
     }
-    if (EDGE) {
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < 8; c++)
-                if (!(r < l.ev && c < l.eh)) d[8 * r + c] = 0;
-    }
 }
 
 // 2-D: `b` holds the two row differences of the step (rows 2s, 2s+1); Dx
 // gives d.
-template <bool EDGE>
-__device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const Lane& l, int lane, int s)
+__device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], int lane)
 {
 #pragma unroll
     for (int r = 0; r < 2; r++) {  // Dx; column 0 takes column 15 of lane-1 (0 at lane 0)
@@ -320,14 +284,6 @@ __device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const
         d[16 * r] = b[16 * r] - (lane == 0 ? 0 : left);
 #pragma unroll
         for (int c = 1; c < 16; c++) d[16 * r + c] = b[16 * r + c] - b[16 * r + c - 1];
-    }
-    if (EDGE) {
-        const bool r1 = 2 * s + 1 < l.ext[0];
-#pragma unroll
-        for (int c = 0; c < 16; c++) {
-            if (!(c < l.eh)) d[c] = 0;
-            if (!(c < l.eh && r1)) d[16 + c] = 0;
-        }
     }
 }
 
@@ -338,7 +294,7 @@ __device__ __forceinline__ void inplane2(const int (&b)[32], int (&d)[32], const
 // nz[b] collects their OR for the flags.
 // Returns whether some delta of the layer needs an escape (only the ESC pass
 // logs them).
-template <int RANK, bool EDGE, bool VEC4, bool ESC, int QM = kQuantGrid>
+template <int RANK, bool VEC4, bool ESC, int QM = kQuantGrid>
 __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g, const Lane& l, int k, Quant inv,
                                       int lane, float (&h)[32], float (&v)[32], uint32_t* Wl, uint32_t (&nz)[16],
                                       float& facc, EscapeLog& log)
@@ -370,23 +326,8 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
 #pragma unroll ESC ? 1 : 4
     for (int t = 0; t < 4; t++) {
         const int s = 4 * k + t;
-        if (EDGE) {
-            const int64_t lo = RANK == 3 ? s : RANK == 2 ? 2 * s : (int64_t)kStepCodes * s;
-            if (lo >= l.ext[0]) {
-#pragma unroll
-                for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] = 0u;
-                continue;
-            }
-        }
         float vn[32];
-        if (t < 3) {
-            bool next = true;
-            if (EDGE) {
-                const int64_t lo = RANK == 3 ? s + 1 : RANK == 2 ? 2 * (s + 1) : (int64_t)kStepCodes * (s + 1);
-                next = lo < l.ext[0];
-            }
-            if (next) load_step<RANK, EDGE, VEC4>(x, g, l, s + 1, lane, vn);
-        }
+        if (t < 3) load_step<RANK, VEC4>(x, g, l, s + 1, vn);
         // keep the steps apart: the scheduler must not pull the next step's
         // arithmetic up to its loads, which would wait on them right away
         __builtin_amdgcn_sched_barrier(0);
@@ -400,7 +341,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
                 a[i] = q[i] - qprev[i];  // Dz
                 qprev[i] = q[i];
             }
-            inplane3<EDGE>(a, d, l, lane);
+            inplane3(a, d, lane);
         } else if (RANK == 2) {
             int b[32];
 #pragma unroll
@@ -409,20 +350,15 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
                 b[16 + c] = q[16 + c] - q[c];
                 qprev[c] = q[16 + c];
             }
-            inplane2<EDGE>(b, d, l, lane, s);
+            inplane2(b, d, lane);
         } else {
             const int left = shift_up1_raw(q[31]);
             d[0] = q[0] - (lane == 0 ? carry1 : left);
 #pragma unroll
             for (int m = 1; m < 32; m++) d[m] = q[m] - q[m - 1];
             carry1 = __builtin_amdgcn_readlane(q[31], 63);
-            if (EDGE) {
-                const int valid = clampi(l.ext[0] - ((int64_t)kStepCodes * s + l.off), 0, 32);
-#pragma unroll
-                for (int m = 0; m < 32; m++)
-                    if (!(m < valid)) d[m] = 0;
-            }
         }
+        if (ESC) mask_outside<RANK>(d, l, s, lane);
         uint32_t P[16];
         esc |= finish_step<ESC>(d, P, log, (uint32_t)s * kStepCodes, lane);
 #pragma unroll
@@ -439,8 +375,7 @@ __device__ __forceinline__ bool layer(const float* __restrict__ x, const Geom& g
     return esc;
 }
 
-// Layer k swept downwards (fast path of odd layers, 2-D and 3-D, chunks not
-// cut by the field's edge).  An odd layer's halo is the top plane of the
+// Layer k swept downwards (fast path of odd layers, 2-D and 3-D).  An odd layer's halo is the top plane of the
 // layer below it, and an even layer's halo the top plane of an odd layer; in
 // this order each halo plane is loaded in the same iteration as by the wave
 // that owns it, so the second load is served by the cache.  `h` holds the top
@@ -462,7 +397,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
     for (int it = 0; it < 4; it++) {
         const int t = 3 - it, s = 4 * k + t;
         float vn[32];
-        if (it < 3) load_step<RANK, false, VEC4>(x, g, l, s - 2, lane, vn);  // s - 2 = 4k - 1 at it = 2: the halo
+        if (it < 3) load_step<RANK, VEC4>(x, g, l, s - 2, vn);  // s - 2 = 4k - 1 at it = 2: the halo
         __builtin_amdgcn_sched_barrier(0);
         int ql[32];  // q of step s - 1
         prequant32<QM>(v, inv, facc, ql);
@@ -474,7 +409,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
                 a[i] = cq[i] - ql[i];  // Dz
                 cq[i] = ql[i];
             }
-            inplane3<false>(a, d, l, lane);
+            inplane3(a, d, lane);
         } else {
             int b[32];
 #pragma unroll
@@ -484,7 +419,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
             }
 #pragma unroll
             for (int i = 0; i < 32; i++) cq[i] = ql[i];
-            inplane2<false>(b, d, l, lane, s);
+            inplane2(b, d, lane);
         }
         uint32_t P[16];
         esc |= finish_step<false>(d, P, log, (uint32_t)s * kStepCodes, lane);
@@ -511,33 +446,29 @@ __device__ __forceinline__ bool swept_down(int k)
 
 // Load the first two steps that layer k of a chunk uses ahead of time: the
 // halo and the first step (upwards), or the top two steps (downwards).
+// Branch-free: both loads are always issued, and one that has nothing to
+// read (no layer k, the halo of layer 0 or of a 1-D layer) gets a range of 0
+// and returns zeros.  A branch here would merge the loads' uniform row
+// offsets at its join, where the compiler keeps them in vector registers and
+// then has to build a loop around every later load that uses them.  The
+// halo or top step is the one another wave reads again (cached), the other
+// one is streamed.
 template <int RANK, bool VEC4>
-__device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom& g, const Lane& l, int k, int lane,
+__device__ __forceinline__ void prefetch(const float* __restrict__ x, const Geom& g, const Lane& l, int k,
                                          float (&h)[32], float (&v)[32], bool down = false)
 {
-    if (down && k < l.L) {
-        load_step<RANK, false, VEC4>(x, g, l, 4 * k + 3, lane, h);
-        load_step<RANK, false, VEC4>(x, g, l, 4 * k + 2, lane, v);
-        return;
-    }
+    const bool live = k < l.L, dn = down && live;
+    if (RANK == 1) {  // no halo step (a 1-D layer's halo is one value)
 #pragma unroll
-    for (int i = 0; i < 32; i++) {  // every path defines both, so no old value stays live
-        h[i] = 0.0f;
-        v[i] = 0.0f;
-    }
-    if (k >= l.L) return;
-    if (l.edge) {
-        if (k > 0 && RANK != 1) load_step<RANK, true, VEC4>(x, g, l, 4 * k - 1, lane, h);
-        load_step<RANK, true, VEC4>(x, g, l, 4 * k, lane, v);
+        for (int i = 0; i < 32; i++) h[i] = 0.0f;
     } else {
-        if (k > 0 && RANK != 1) load_step<RANK, false, VEC4>(x, g, l, 4 * k - 1, lane, h);
-        load_step<RANK, false, VEC4>(x, g, l, 4 * k, lane, v);
+        load_step_as<RANK, VEC4, false>(x, g, l, dn ? 4 * k + 3 : 4 * k - 1, live && (dn || k > 0), h);
     }
+    load_step_as<RANK, VEC4, RANK == 3>(x, g, l, dn ? 4 * k + 2 : 4 * k, live, v);
 }
 
-// Out-of-line layer pass for the uncommon cases: a chunk cut by the field's
-// edge, or a layer whose deltas need escapes (computed again with the escape
-// codes).  It loads its own inputs, writes the layer's bricks to Wl, logs the
+// Out-of-line layer pass for the uncommon case of a layer whose deltas need
+// escapes (computed again with the escape codes).  It loads its own inputs, writes the layer's bricks to Wl, logs the
 // escape pairs to `pairs` (at most `room` of them; null: count only) and
 // returns (escape count << 32) | max-|p| bits.  The geometry is read from the copy
 // in the scratch so that nothing large crosses the call.  It stays a real
@@ -551,12 +482,11 @@ __device__ __noinline__ uint64_t layer_slow(const float* __restrict__ x, const u
     const Geom g = *reinterpret_cast<const Geom*>(scr + kScratchGeomOff);
     const Lane l = lane_geo<RANK>(g, c, lane);
     float h[32], v[32];
-    prefetch<RANK, VEC4>(x, g, l, k, lane, h, v);
+    prefetch<RANK, VEC4>(x, g, l, k, h, v);
     uint32_t nz[16];
     float facc = 0.0f;
     EscapeLog log{pairs, 0, room};
-    if (l.edge) layer<RANK, true, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
-    else layer<RANK, false, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
+    layer<RANK, VEC4, true, QM>(x, g, l, k, inv, lane, h, v, Wl, nz, facc, log);
     return ((uint64_t)(uint32_t)log.count << 32) | __float_as_uint(facc);
 }
 
@@ -633,10 +563,33 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, const ui
     return nout;
 }
 
+// A layer of a chunk cut by the field's edge, after the fast pass: its
+// cells outside the field were loaded as other chunks' values (or zeros past
+// the field's end), so their codes are cleared in the layer's plane words in
+// LDS (bit i of each word is code i of the lane's patch); the caller then
+// gathers the flags' nonzero bits again.  Such a cell's delta may also have
+// reported an escape; the layer has then taken the logging pass instead,
+// which zeroes those deltas before it looks for escapes.  A real call, with
+// plain arguments and LDS only: inlined, or with arrays passed to it, it
+// pushes the fast path into spills.
+template <int RANK>
+__device__ __noinline__ void mask_layer(uint32_t* Wl, int64_t e0, int64_t e1, int64_t e2, uint32_t off, int k, int lane)
+{
+    Lane l;
+    l.ext[0] = e0;
+    l.ext[1] = e1;
+    l.ext[2] = e2;
+    l.off = off;
+    for (int t = 0; t < 4; t++) {
+        const uint32_t keep = keep_bits<RANK>(l, 4 * k + t, lane);
+#pragma unroll
+        for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] &= keep;
+    }
+}
+
 // Wave `wave`'s layer of chunk c: bricks into S.w[wave], its brick and
 // escape counts into S.  `h` / `v` hold the prefetched halo and first step
-// unless the chunk is cut by the field's edge (the out-of-line pass then
-// loads its own).  F receives the layer's per-plane ballots and `myflag` the
+// (the top two steps of a layer swept downwards).  F receives the layer's per-plane ballots and `myflag` the
 // flag word lane b < 16 stores; returns the layer's escape count.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, const uint8_t* __restrict__ scr, const Geom& g,
@@ -648,20 +601,25 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, const ui
     uint32_t* Wl = S.w[wave];
     EscapeLog log{nullptr, 0, 0};
     if (wave < l.L) {
-        bool slow = l.edge;
-        if (!slow) {
-            if constexpr (RANK >= 2) {
-                slow = swept_down<RANK>(wave)
-                           ? layer_rev<RANK, VEC4, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
-                           : layer<RANK, false, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
-            } else {
-                slow = layer<RANK, false, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
-            }
+        bool slow;
+        if constexpr (RANK >= 2) {
+            slow = swept_down<RANK>(wave)
+                       ? layer_rev<RANK, VEC4, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
+                       : layer<RANK, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
+            if (!slow && l.edge)  // uniform: clear the codes of cells outside the field
+                mask_layer<RANK>(Wl, l.ext[0], l.ext[1], l.ext[2], l.off, wave, lane);
+        } else {
+            // 1-D: only a field's last chunk is cut by its edge; it takes the
+            // logging pass, which masks the deltas itself (a mask call here
+            // measured as spills in the 1-D fast path)
+            slow = layer<RANK, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log) || l.edge;
         }
-        if (slow) {  // edge chunk, or escapes to log
+        if (slow) {  // escapes to log
             const uint64_t r = layer_slow<RANK, VEC4, QM>(x, scr, c, wave, inv, lane, Wl, nullptr, 0);
             log.count = (int)(r >> 32);
             facc = __builtin_elementwise_maximum(facc, __uint_as_float((uint32_t)r));
+        }
+        if (slow || l.edge) {  // the layer's words were rewritten in LDS: their nonzero bits again
 #pragma unroll
             for (int b = 0; b < 16; b++)
                 nz[b] = Wl[(b * 4) * 64 + lane] | Wl[(b * 4 + 1) * 64 + lane] | Wl[(b * 4 + 2) * 64 + lane] |
@@ -945,6 +903,11 @@ __device__ __forceinline__ RelParams fold_params(const uint8_t* __restrict__ scr
         hi = max(hi, s_red[1][i]);
         bad |= s_red[2][i];
     }
+    // the same on every lane: kept scalar, so that a branch on the result is
+    // uniform and nothing after it is treated as divergent
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    bad = __builtin_amdgcn_readfirstlane(bad);
     __syncthreads();  // s_red may be reused by the caller's next fold
     RelParams r{0u, 0.0f, 0.0f, 0.0f, 0.0f};
     if (bad) {
