@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_batch_clear_err(const DecompressJob* __
     if (j < n_jobs && jobs[j].err) *jobs[j].err = 0u;
 }
 
-__global__ __launch_bounds__(64) void k_batch_decompress(const DecompressJob* __restrict__ jobs,
+__global__ __launch_bounds__(64, 2) void k_batch_decompress(const DecompressJob* __restrict__ jobs,
                                                          const int32_t* __restrict__ chunk_job)
 {
     __shared__ float tile[kTileFloats];

@@ -160,6 +160,17 @@ __device__ __forceinline__ void store_run_masked(T* __restrict__ p, const int* q
 // 2-D and 1-D, the step's 2048 values in order with 4 floats of padding after
 // every 32 (both paddings spread a wave's 16-byte accesses over the banks)
 constexpr int kTilePitch = 68;
+
+// Orders one wave's LDS accesses to its own tile (writes before the reads of
+// other lanes, reads before the next rewrite): the compiler may not move
+// memory operations across it, and the wave waits for its LDS operations.
+// A workgroup barrier is not needed (no other wave touches the tile) and not
+// possible where the waves of a workgroup run different numbers of steps.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
 constexpr int kTileFloats = 2048 + 4 * (2048 / 32);
 static_assert(32 * kTilePitch <= kTileFloats, "the 3-D tile fits");
 __device__ __forceinline__ int run_slot(int i) { return i + 4 * (i >> 5); }
@@ -171,7 +182,7 @@ __device__ __forceinline__ int run_slot(int i) { return i + 4 * (i >> 5); }
 // contiguous run).
 __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, uint32_t row_bytes, int lane)
 {
-    __syncthreads();  // one wave: orders the tile's writes before its reads
+    wave_lds_sync();  // orders the tile's writes before its reads
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, -1, kBufferFlags);
 #pragma unroll
     for (int i = 0; i < 8; i++) {
@@ -180,7 +191,7 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, u
         const uint32_t soff = (uint32_t)(i >> 2) * row_bytes + 1024u * (uint32_t)(i & 3);
         __builtin_amdgcn_raw_buffer_store_b128(w, rs, 16u * (uint32_t)lane, soff, kCacheStreamStore);
     }
-    __syncthreads();  // the tile is rewritten by the next step
+    wave_lds_sync();  // the tile is rewritten by the next step
 }
 
 // The same for a 2-D step of a chunk cut by the field's edge: `rows` (1 or
@@ -190,7 +201,7 @@ __device__ __forceinline__ void store_tile_runs(const float* tile, void* base, u
 __device__ __forceinline__ void store_tile_runs_edge(const float* tile, void* base, uint32_t nx, uint32_t rows,
                                                      uint32_t cols, int lane)
 {
-    __syncthreads();  // one wave: orders the tile's writes before its reads
+    wave_lds_sync();  // orders the tile's writes before its reads
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(4u * ((rows - 1) * nx + cols)), kBufferFlags);
 #pragma unroll
@@ -201,7 +212,7 @@ __device__ __forceinline__ void store_tile_runs_edge(const float* tile, void* ba
         const uint32_t voff = row < rows && col < cols ? 4u * (row * nx + col) : 0x80000000u;
         __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 0u, 0);
     }
-    __syncthreads();  // the tile is rewritten by the next step
+    wave_lds_sync();  // the tile is rewritten by the next step
 }
 
 // The fp64 output's tiles (twice the words; the caller's LDS holds
@@ -224,19 +235,80 @@ __device__ __forceinline__ void store_nt2(double* p, double a, double b)
 // doubles 1024 r .. start at element r * row_elems from `base`
 __device__ __forceinline__ void store_tile_runs64(const double* tile, double* base, int64_t row_elems, int lane)
 {
-    __syncthreads();  // one wave: orders the tile's writes before its reads
+    wave_lds_sync();  // orders the tile's writes before its reads
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         const double2 v = *reinterpret_cast<const double2*>(tile + run_slot64(128 * i + 2 * lane));
         store_nt2(base + (int64_t)(i >> 3) * row_elems + 128 * (i & 7) + 2 * lane, v.x, v.y);
     }
-    __syncthreads();  // the tile is rewritten by the next step
+    wave_lds_sync();  // the tile is rewritten by the next step
 }
 
-template <int RANK, bool VEC4, bool PW, typename T>
-__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, uint64_t s_bytes, T* __restrict__ y,
-                                                 const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile)
+// 3-D: inclusive prefix of one plane of deltas along x, then y (the lane's
+// 4x8 patch at rows 4 py.., columns 8 px..): inside the patch, with the carry
+// across the lanes 8 apart (DPP and lane swaps) along x and across lanes -1,
+// -2, -4 (a shift inside the 16-lane row) along y.
+__device__ __forceinline__ void plane_prefix3(int (&d)[32], int lane)
 {
+    const int py = lane & 7;
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int cc = 1; cc < 8; cc++) d[8 * r + cc] += d[8 * r + cc - 1];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int ex_ = excl_scan_stride8(d[8 * r + 7], lane);
+#pragma unroll
+        for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += ex_;
+    }
+#pragma unroll
+    for (int r = 1; r < 4; r++)
+#pragma unroll
+        for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += d[8 * (r - 1) + cc];
+#pragma unroll
+    for (int cc = 0; cc < 8; cc++) {
+        const int C = d[24 + cc];
+        int inc = C;
+        int tv = row_shr<1>(inc);
+        inc += py >= 1 ? tv : 0;
+        tv = row_shr<2>(inc);
+        inc += py >= 2 ? tv : 0;
+        tv = row_shr<4>(inc);
+        inc += py >= 4 ? tv : 0;
+        const int ex_ = inc - C;
+#pragma unroll
+        for (int r = 0; r < 4; r++) d[8 * r + cc] += ex_;
+    }
+}
+
+// 2-D: inclusive prefix along x of one row held as 16 values per lane (lane
+// l has columns 16 l .. 16 l + 15)
+__device__ __forceinline__ void row_prefix2(int* d, int lane)
+{
+#pragma unroll
+    for (int cc = 1; cc < 16; cc++) d[cc] += d[cc - 1];
+    const int tot = d[15];
+    const int ex_ = wave_incl_scan(tot, lane) - tot;
+#pragma unroll
+    for (int cc = 0; cc < 16; cc++) d[cc] += ex_;
+}
+
+// Decompress chunk c of a field.  NW = 1: one wave (the workgroup) runs
+// every layer.  NW = 2 or 4: the chunk's workgroup has NW waves, and wave
+// `wave` runs layers 4/NW * wave .. (a field with few chunks, whose
+// latency is set by a chunk's serial steps).  The prefix sums along the step
+// dimension need what the layers below contributed: each wave first decodes
+// its layers once and sums their deltas over the steps; the in-plane prefix of
+// that sum is its contribution to the carry (the prefix is linear), left in
+// `xch` (LDS, NW x 2048 ints).  After a workgroup barrier, wave w adds those of
+// waves 0 .. w-1 to get its starting carry, then runs its layers as the single
+// wave would.
+template <int RANK, bool VEC4, bool PW, typename T, int NW>
+__device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, uint64_t s_bytes, T* __restrict__ y,
+                                                 const Geom& g, uint32_t* d_err, int64_t c, int lane, float* tile,
+                                                 int wave, int* xch)
+{
+    constexpr bool SPLIT = NW > 1;
     constexpr bool F64 = sizeof(T) == 8;
     constexpr bool INT = std::is_integral_v<T>;
     const uint32_t hdr_err = check_header(s, g, RANK, F64 ? 1 : 0, INT ? 1 : 0, s_bytes);
@@ -288,7 +360,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
         // holds no register and nothing waits for it (the first step's wait
         // for its own words, issued after these, covers them in order).
         __shared__ uint32_t touch_dump[64];
-        for (uint32_t o = 0; o < 16u * nnz; o += 8192u)
+        for (uint32_t o = 8192u * (uint32_t)wave; o < 16u * nnz; o += (uint32_t)NW * 8192u)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)touch_dump, 4,
                                                      o + 128u * (uint32_t)lane, 0, 0, 0);
     }
@@ -301,10 +373,11 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     constexpr uint32_t kZeroBrick = 0x80000000u;
     uint32_t voff[16];
     uint32_t cur = 0;
-    auto layer_offsets = [&](int k) {  // past the last layer: all bricks zero
+    int k0 = 0, k1 = L;  // the layers this wave runs
+    auto layer_offsets = [&](int k) {  // past the wave's last layer: all bricks zero
 #pragma unroll
         for (int b = 0; b < 16; b++) {
-            const uint64_t f = k < L ? F[k * kPlanes + b] : 0ull;
+            const uint64_t f = k < k1 ? F[k * kPlanes + b] : 0ull;
             voff[b] = ((f >> lane) & 1ull) ? 16u * (cur + mbcnt(f)) : kZeroBrick;
             cur += (uint32_t)__popcll(f);
         }
@@ -324,6 +397,88 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
 #pragma unroll
     for (int i = 0; i < 16; i++) carry2[i] = 0;
 
+    if constexpr (SPLIT) {
+        k0 = (kLayers / NW) * wave;
+        k1 = k0 + kLayers / NW < L ? k0 + kLayers / NW : L;
+        // bricks and escape pairs of the layers below this one (the pairs are
+        // in code-index order: those with an index below the layer's first)
+        for (int i = 0; i < (k0 < L ? k0 : L) * kPlanes; i++) cur += (uint32_t)__popcll(F[i]);
+        if (nout && k0 > 0) {
+            const uint32_t first = (uint32_t)(4 * k0) * kStepCodes;
+            uint32_t n = 0;
+            for (uint32_t j = (uint32_t)lane; j < nout; j += 64) n += pairs[2 * j] < first ? 1u : 0u;
+#pragma unroll
+            for (int sh = 32; sh > 0; sh >>= 1) n += (uint32_t)__shfl_xor((int)n, sh);
+            seen = n;
+        }
+        if (k0 < L) {
+            // pass 1: the deltas of the wave's layers summed over their steps,
+            // then their in-plane prefix (3-D: 32 per lane; 2-D: 16 per lane,
+            // both rows of each step; 1-D: the total)
+            const uint32_t cur0 = cur;
+            int acc[32];
+#pragma unroll
+            for (int i = 0; i < 32; i++) acc[i] = 0;
+            uint32_t seen1 = seen;
+#pragma unroll 1
+            for (int k = k0; k < k1; k++) {
+                layer_offsets(k);
+                uint32_t Wp[4][16];
+#pragma unroll
+                for (int t = 0; t < 4; t++) load_words(t, Wp[t]);
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    uint32_t P[16];
+#pragma unroll
+                    for (int b = 0; b < 15; b++) P[b] = Wp[t][b];
+                    const uint32_t sgn = Wp[t][15];
+                    P[15] = 0u;
+                    transpose16(P);
+                    int d[32];
+                    decode_codes(P, sgn, d);
+                    if (nout)
+                        esc_bad |= apply_escapes(P, sgn, d, pairs, nout, seen1, (uint32_t)(4 * k + t) * kStepCodes, lane);
+#pragma unroll
+                    for (int i = 0; i < 32; i++) acc[i] += d[i];
+                }
+            }
+            cur = cur0;
+            int* xw = xch + 2048 * wave;
+            if (RANK == 3) {
+                plane_prefix3(acc, lane);
+#pragma unroll
+                for (int i = 0; i < 32; i++) xw[64 * i + lane] = acc[i];
+            } else if (RANK == 2) {
+#pragma unroll
+                for (int cc = 0; cc < 16; cc++) acc[cc] += acc[16 + cc];
+                row_prefix2(acc, lane);
+#pragma unroll
+                for (int cc = 0; cc < 16; cc++) xw[64 * cc + lane] = acc[cc];
+            } else {
+                int tot = 0;
+#pragma unroll
+                for (int i = 0; i < 32; i++) tot += acc[i];
+#pragma unroll
+                for (int sh = 32; sh > 0; sh >>= 1) tot += __shfl_xor(tot, sh);
+                if (lane == 0) xw[0] = tot;
+            }
+        }
+        __syncthreads();  // every wave reaches it: the checks above are the same for the whole chunk
+        if (k0 >= L) return;
+        for (int j = 0; j < wave; j++) {
+            const int* xj = xch + 2048 * j;
+            if (RANK == 3) {
+#pragma unroll
+                for (int i = 0; i < 32; i++) carry3[i] += xj[64 * i + lane];
+            } else if (RANK == 2) {
+#pragma unroll
+                for (int cc = 0; cc < 16; cc++) carry2[cc] += xj[64 * cc + lane];
+            } else {
+                carry1 += xj[0];
+            }
+        }
+    }
+
     // The words of a step are loaded two steps ahead: the wait for them then
     // leaves the previous step's stores outstanding (the counter of
     // outstanding vector memory operations covers stores too, in issue order).
@@ -335,7 +490,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
     uint32_t W[4][16];
 #pragma unroll
     for (int b = 0; b < 16; b++) voff[b] = kZeroBrick;
-    for (int k = -1; k < L; k++) {
+    for (int k = k0 - 1; k < k1; k++) {
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             if (t == 2) layer_offsets(k + 1);  // the last load of layer k was issued at t = 1
@@ -343,7 +498,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             __builtin_amdgcn_sched_barrier(0);
             const int st = 4 * k + t;
             const int64_t step_lo = RANK == 3 ? st : RANK == 2 ? 2 * st : (int64_t)kStepCodes * st;
-            if (k < 0 || step_lo >= ext[0]) continue;
+            if (k < k0 || step_lo >= ext[0]) continue;
             uint32_t P[16];
 #pragma unroll
             for (int b = 0; b < 15; b++) P[b] = W[t][b];
@@ -355,37 +510,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             if (nout) esc_bad |= apply_escapes(P, sgn, d, pairs, nout, seen, (uint32_t)st * kStepCodes, lane);
 
             if (RANK == 3) {
-                // prefix along x inside the patch, carry across the lanes 8 apart (DPP and lane swaps)
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-#pragma unroll
-                    for (int cc = 1; cc < 8; cc++) d[8 * r + cc] += d[8 * r + cc - 1];
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int ex_ = excl_scan_stride8(d[8 * r + 7], lane);
-#pragma unroll
-                    for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += ex_;
-                }
-                // prefix along y inside the patch, carry across lanes -1, -2, -4
-                // (within a group of 8 lanes: a shift inside the 16-lane row)
-#pragma unroll
-                for (int r = 1; r < 4; r++)
-#pragma unroll
-                    for (int cc = 0; cc < 8; cc++) d[8 * r + cc] += d[8 * (r - 1) + cc];
-#pragma unroll
-                for (int cc = 0; cc < 8; cc++) {
-                    const int C = d[24 + cc];
-                    int inc = C;
-                    int tv = row_shr<1>(inc);
-                    inc += py >= 1 ? tv : 0;
-                    tv = row_shr<2>(inc);
-                    inc += py >= 2 ? tv : 0;
-                    tv = row_shr<4>(inc);
-                    inc += py >= 4 ? tv : 0;
-                    const int ex_ = inc - C;
-#pragma unroll
-                    for (int r = 0; r < 4; r++) d[8 * r + cc] += ex_;
-                }
+                plane_prefix3(d, lane);
                 // prefix along z: previous plane of the same patch
 #pragma unroll
                 for (int i = 0; i < 32; i++) {
@@ -412,7 +537,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                             make_float4(tile_val<PW, T>(d[8 * r + 4], ebx2, step), tile_val<PW, T>(d[8 * r + 5], ebx2, step),
                                         tile_val<PW, T>(d[8 * r + 6], ebx2, step), tile_val<PW, T>(d[8 * r + 7], ebx2, step));
                     }
-                    __syncthreads();  // one wave: orders the tile's writes before its reads
+                    wave_lds_sync();  // orders the tile's writes before its reads
                     T* plane = y + (z * g.n[1] + org[1]) * g.n[2] + org[2];
                     if (!edge) {
                         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(plane, (short)0, -1, kBufferFlags);
@@ -445,7 +570,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                             __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, 0u, 0);
                         }
                     }
-                    __syncthreads();  // the tile is rewritten by the next step
+                    wave_lds_sync();  // the tile is rewritten by the next step
                 } else if constexpr (VEC4 && F64) {
                     // through LDS as above: every store writes 2 whole rows of 64 doubles
                     double* t64 = reinterpret_cast<double*>(tile);
@@ -458,7 +583,7 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                                 make_double2(dequant<PW>(d[8 * r + 2 * j], ebx2, step),
                                              dequant<PW>(d[8 * r + 2 * j + 1], ebx2, step));
                     }
-                    __syncthreads();  // one wave: orders the tile's writes before its reads
+                    wave_lds_sync();  // orders the tile's writes before its reads
                     T* base = y + (z * g.n[1] + org[1]) * g.n[2] + org[2];
 #pragma unroll
                     for (int i = 0; i < 16; i++) {
@@ -466,23 +591,14 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
                         const double2 v = *reinterpret_cast<const double2*>(t64 + row * kTilePitch64 + col);
                         store_nt2(base + (int64_t)row * g.n[2] + col, v.x, v.y);
                     }
-                    __syncthreads();  // the tile is rewritten by the next step
+                    wave_lds_sync();  // the tile is rewritten by the next step
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; r++) store_run<8, VEC4, PW>(y + ((z * g.n[1] + y0 + r) * g.n[2] + x0), d + 8 * r, ebx2, step);
                 }
             } else if (RANK == 2) {
-#pragma unroll
-                for (int r = 0; r < 2; r++)
-#pragma unroll
-                    for (int cc = 1; cc < 16; cc++) d[16 * r + cc] += d[16 * r + cc - 1];
-#pragma unroll
-                for (int r = 0; r < 2; r++) {
-                    const int tot = d[16 * r + 15];
-                    const int ex_ = wave_incl_scan(tot, lane) - tot;
-#pragma unroll
-                    for (int cc = 0; cc < 16; cc++) d[16 * r + cc] += ex_;
-                }
+                row_prefix2(d, lane);
+                row_prefix2(d + 16, lane);
 #pragma unroll
                 for (int cc = 0; cc < 16; cc++) {
                     d[cc] += carry2[cc];
@@ -561,27 +677,33 @@ __device__ __forceinline__ void decompress_chunk(const uint8_t* __restrict__ s, 
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    if (nout && (esc_bad || seen != nout)) {
+    // every escape code had its pair, and (the wave that ran the last layer)
+    // no pair is left over
+    if (nout && (esc_bad || (k1 == L && seen != nout))) {
         if (lane == 0 && d_err) atomicCAS(d_err, 0u, 6u);
     }
 }
 
 // Decompress chunk c with the stream's quantizer (the mode byte is uniform:
-// one of the two bodies runs).
-template <int RANK, bool VEC4, typename T>
+// one of the two bodies runs).  NW > 1: the form with NW waves per chunk
+// (fp32 output only), `tile` this wave's own tile and `xch` the workgroup's
+// carry exchange.
+template <int RANK, bool VEC4, int NW = 1, typename T>
 __device__ __forceinline__ void decompress_chunk_any(const uint8_t* __restrict__ s, uint64_t s_bytes,
                                                      T* __restrict__ y, const Geom& g, uint32_t* d_err, int64_t c,
-                                                     int lane, float* tile)
+                                                     int lane, float* tile, int wave = 0, int* xch = nullptr)
 {
+    static_assert(NW == 1 || std::is_same_v<T, float>, "the split forms write fp32 through fp32 tiles");
+    static_assert(NW == 1 || NW == 2 || NW == 4, "a chunk's 4 layers are shared evenly");
     if constexpr (sizeof(T) == 8 || std::is_integral_v<T>) {
         // fp64 (grid modes only), or the integers of a field-global stream
         // (dequantized after the carries, in any mode)
-        decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
+        decompress_chunk<RANK, VEC4, false, T, 1>(s, s_bytes, y, g, d_err, c, lane, tile, 0, nullptr);
     } else {
         // the mode byte from its (uniform, scalar-loaded) header word
         const uint32_t mode = (reinterpret_cast<const uint32_t*>(s)[kOffEbMode / 4] >> (8 * (kOffEbMode % 4))) & 0xFFu;
-        if (mode == 2) decompress_chunk<RANK, VEC4, true, T>(s, s_bytes, y, g, d_err, c, lane, tile);
-        else decompress_chunk<RANK, VEC4, false, T>(s, s_bytes, y, g, d_err, c, lane, tile);
+        if (mode == 2) decompress_chunk<RANK, VEC4, true, T, NW>(s, s_bytes, y, g, d_err, c, lane, tile, wave, xch);
+        else decompress_chunk<RANK, VEC4, false, T, NW>(s, s_bytes, y, g, d_err, c, lane, tile, wave, xch);
     }
 }
 

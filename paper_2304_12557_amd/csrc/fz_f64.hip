@@ -217,7 +217,7 @@ hipError_t launch_f64_front(const double* x, uint8_t* out, const Geom& g, int mo
 
 // ------------------------------------------------------------ decompression
 template <int RANK, bool VEC4>
-__global__ __launch_bounds__(64) void k_decompress64(const uint8_t* __restrict__ s, uint64_t sb, double* __restrict__ y,
+__global__ __launch_bounds__(64, 2) void k_decompress64(const uint8_t* __restrict__ s, uint64_t sb, double* __restrict__ y,
                                                      Geom g, uint32_t* d_err)
 {
     __shared__ __attribute__((aligned(16))) float tile[kTileFloats64];

@@ -147,7 +147,7 @@ hipError_t launch_face(const float* x, uint8_t* out, const Geom& g, hipStream_t 
 
 // ------------------------------------------------------------ decompression
 template <int RANK, bool VEC4>
-__global__ __launch_bounds__(64) void k_decompress_int(const uint8_t* __restrict__ s, uint64_t sb,
+__global__ __launch_bounds__(64, 2) void k_decompress_int(const uint8_t* __restrict__ s, uint64_t sb,
                                                        int32_t* __restrict__ y, Geom g, uint32_t* d_err)
 {
     __shared__ float tile[kTileFloats];
