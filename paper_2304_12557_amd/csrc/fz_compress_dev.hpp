@@ -13,7 +13,9 @@
 // the workgroup's staging slot with coalesced 16-byte writes.  A layer whose
 // deltas need escapes is computed again out of line; its (index, delta) pairs
 // are written after the workgroup barrier, once every layer's count is known,
-// straight to their place behind the chunk's bricks.  One chunk later, when
+// straight to their place behind the chunk's bricks.  A chunk cut by the
+// field's edge runs the same code; the codes of its cells outside the field
+// are cleared afterwards.  One chunk later, when
 // a look-back over the published chunk sizes (the device-wide prefix sum of
 // Sec. 3.4) has given the chunk its offset, the slot is copied there.
 #pragma once
@@ -437,7 +439,7 @@ __device__ __forceinline__ bool layer_rev(const float* __restrict__ x, const Geo
     return esc;
 }
 
-// Whether layer k of a chunk not cut by the field's edge is swept downwards.
+// Whether layer k of a chunk is swept downwards.
 template <int RANK>
 __device__ __forceinline__ bool swept_down(int k)
 {
