@@ -186,11 +186,16 @@ __global__ __launch_bounds__(64, 2) void k_batch_decompress(const DecompressJob*
 // ------------------------------------------------------------------- plans
 namespace {
 
+// launch class of a field: rank and whether whole 16-byte accesses apply
+// (decompression: 16-byte aligned output rows of whole 16-byte pieces;
+// compression: 4-byte aligned input, vec_loads)
 int vec_key(const void* p, const Geom& g)
 {
     const bool vec4 = (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
     return g.rank * 2 + (vec4 ? 1 : 0);
 }
+
+int compress_key(const void* p, const Geom& g) { return g.rank * 2 + (vec_loads(p) ? 1 : 0); }
 
 
 }  // namespace
@@ -345,7 +350,7 @@ int plan_compress(Plan* Pp, int n, const fz_compress_job* jobs)
         J.h = header_image(J.g, eb, q.eb_mode, ebx2, inv);
         J.eb = eb;
         J.rel = q.eb_mode == FZ_EB_REL;
-        J.key = vec_key(q.d_in, J.g);
+        J.key = compress_key(q.d_in, J.g);
         J.chunk0 = P.class_chunks[J.key];
         P.class_chunks[J.key] += J.g.n_chunks;
         chunks += J.g.n_chunks;

@@ -132,6 +132,15 @@ int64_t minmax_blocks(int64_t n)
 
 static hipError_t mark(hipEvent_t e, hipStream_t st) { return e ? hipEventRecord(e, st) : hipSuccess; }
 
+// Whether the compression kernels may read the field with 16-byte loads (the
+// VEC4 instantiations): whenever its values are 4-byte aligned, whatever the
+// row length.  gfx950 buffer loads need only 4-byte alignment, and their range
+// is checked per dword (measured: a 16-byte load straddling the end of the
+// range returns the dwords inside it and zeros for the rest), so a load that
+// runs past the field's last value still returns that value.  The values a
+// lane reads past its chunk's rows belong to other chunks and are masked.
+bool vec_loads(const void* x) { return (reinterpret_cast<uintptr_t>(x) & 3) == 0; }
+
 template <int RANK, bool VEC4, int QM>
 static hipError_t launch_rank(const float* x, uint8_t* out, uint8_t* scr, const Geom& g, hipStream_t st,
                               const Timing* t = nullptr, double rel_eb = 0.0, int nparts = 0)
@@ -168,11 +177,11 @@ static hipError_t launch_init(uint8_t* out, uint8_t* scr, const Geom& g, const H
 // the compression kernel on the integer buffer at g.q_off (scratch inside the output buffer)
 static hipError_t launch_main_int(uint8_t* out, const Geom& g, hipStream_t st)
 {
-    // the integer buffer is 256-byte aligned: whole-vector loads whenever the rows allow them
+    // the integer buffer is 256-byte aligned: 16-byte loads (they need only
+    // 4-byte alignment, see vec_loads)
     const float* qf = reinterpret_cast<const float*>(out + g.q_off);
     uint8_t* scr = out + g.scratch_off;
-    const bool vec4 = g.rank == 1 || (g.n[g.rank - 1] & 3) == 0;
-    switch (g.rank * 2 + (vec4 ? 1 : 0)) {
+    switch (g.rank * 2 + 1) {
         case 7: return launch_rank<3, true, kQuantInt>(qf, out, scr, g, st);
         case 6: return launch_rank<3, false, kQuantInt>(qf, out, scr, g, st);
         case 5: return launch_rank<2, true, kQuantInt>(qf, out, scr, g, st);
@@ -234,7 +243,7 @@ hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geo
         if ((e = launch_init(out, scr, g, h, st)) != hipSuccess) return e;
         if (t && (e = mark(t->range_begin, st)) != hipSuccess) return e;
     }
-    const bool vec4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 && (g.rank == 1 || (g.n[g.rank - 1] & 3) == 0);
+    const bool vec4 = vec_loads(x);
     if (mode == FZ_EB_PWREL) {
         switch (g.rank * 2 + (vec4 ? 1 : 0)) {
             case 7: return launch_rank<3, true, kQuantPw>(x, out, scr, g, st, t);

@@ -120,7 +120,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t step_rsrc(const float* __restr
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, range, kBufferFlags);
 }
 
-// NT: a nontemporal (streaming) load, for values this chunk reads only once
+// CNT values from voff + soff; VEC4: in 16-byte loads, which need only 4-byte
+// alignment and are range-checked per dword (the host's vec_loads); else one
+// load per value.  NT: a nontemporal (streaming) load, for values this chunk
+// reads only once.
 template <int CNT, bool VEC4, bool NT = false>
 __device__ __forceinline__ void load_run(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float* v)
 {

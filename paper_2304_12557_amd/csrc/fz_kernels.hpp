@@ -44,6 +44,8 @@ hipError_t launch_decompress_global(const uint8_t* s, uint64_t sb, float* y, con
                                     void* work, hipStream_t st);
 size_t global_work_bytes(const Geom& g);
 
+// whether compression may read a field at x with 16-byte loads (4-byte aligned values)
+bool vec_loads(const void* x);
 // blocks of the REL range pass of a field of n values
 int64_t minmax_blocks(int64_t n);
 // header image of a stream (magic, version, dims, eb, chunk box, ...)
