@@ -886,12 +886,25 @@ __device__ __forceinline__ RelParams fold_params(const uint8_t* __restrict__ scr
                                                  int nparts)
 {
     __shared__ uint32_t s_red[3][16];
-    const uint32_t* part = reinterpret_cast<const uint32_t*>(scratch + g.scr_minmax);
+    // the partials (16 B each) in 16-byte loads, 8 per thread in flight
+    // together: every compression workgroup folds them before its first
+    // chunk, and one load at a time cost a cache round trip per 256 partials
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(scratch + g.scr_minmax), (short)0, 16 * nparts, kBufferFlags);
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, bad = 0u;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        lo = min(lo, part[4 * i]);
-        hi = max(hi, part[4 * i + 1]);
-        bad |= part[4 * i + 2];
+    for (int i0 = 0; i0 < nparts; i0 += 8 * (int)blockDim.x) {
+        fz_u32x4 t[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            t[k] = __builtin_amdgcn_raw_buffer_load_b128(rp, 16u * (uint32_t)(i0 + k * blockDim.x + threadIdx.x), 0u, 0);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (i0 + k * (int)blockDim.x + (int)threadIdx.x < nparts) {
+                lo = min(lo, t[k].x);
+                hi = max(hi, t[k].y);
+                bad |= t[k].z;
+            }
+        }
     }
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {
