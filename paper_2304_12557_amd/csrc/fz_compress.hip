@@ -181,13 +181,10 @@ static hipError_t launch_main_int(uint8_t* out, const Geom& g, hipStream_t st)
     // 4-byte alignment, see vec_loads)
     const float* qf = reinterpret_cast<const float*>(out + g.q_off);
     uint8_t* scr = out + g.scratch_off;
-    switch (g.rank * 2 + 1) {
-        case 7: return launch_rank<3, true, kQuantInt>(qf, out, scr, g, st);
-        case 6: return launch_rank<3, false, kQuantInt>(qf, out, scr, g, st);
-        case 5: return launch_rank<2, true, kQuantInt>(qf, out, scr, g, st);
-        case 4: return launch_rank<2, false, kQuantInt>(qf, out, scr, g, st);
-        case 3: return launch_rank<1, true, kQuantInt>(qf, out, scr, g, st);
-        default: return launch_rank<1, false, kQuantInt>(qf, out, scr, g, st);
+    switch (g.rank) {
+        case 3: return launch_rank<3, true, kQuantInt>(qf, out, scr, g, st);
+        case 2: return launch_rank<2, true, kQuantInt>(qf, out, scr, g, st);
+        default: return launch_rank<1, true, kQuantInt>(qf, out, scr, g, st);
     }
 }
 

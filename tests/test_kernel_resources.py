@@ -35,10 +35,14 @@ def family(res, prefix):
     return out
 
 
-@pytest.mark.parametrize("prefix,count", [("_ZN2fz10k_compressI", 18), ("_ZN2fz16k_batch_compressI", 6)])
+# the per-field kernel: 3 ranks x (16-byte loads, or one load per value for a
+# misaligned pointer) x 2 fp32 quantizers, plus 3 ranks on the integers of the
+# fp64 and field-global paths (always 16-byte loads); the batched one: 3 ranks
+# x 2 load widths
+@pytest.mark.parametrize("prefix,count", [("_ZN2fz10k_compressI", 15), ("_ZN2fz16k_batch_compressI", 6)])
 def test_compression_two_workgroups_per_cu(res, prefix, count):
     ks = family(res, prefix)
-    assert len(ks) == count, sorted(ks)  # every (rank, row alignment[, quantizer]) instantiation
+    assert len(ks) == count, sorted(ks)
     for k, v in ks.items():
         assert v["waves_per_simd"] >= 2, (k, v)
         assert v["lds_bytes"] <= 80 * 1024, (k, v)
