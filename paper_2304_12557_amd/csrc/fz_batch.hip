@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
     if (threadIdx.x == 0) {
         S.ticket = atomicAdd(ticket, 1u);
         S.err = 0;
+        S.arrived = 0;
     }
     __syncthreads();
     int64_t t = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -125,13 +126,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_compress(const CompressJob* __
 #pragma unroll
             for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
         }
-        uint32_t units = 0;
-        if (!skip) {
-            units = chunk_units(S);
-            if (threadIdx.x == 0)
-                publish_state(reinterpret_cast<uint64_t*>(scr + kScratchStateOff) + c,
-                              kFlagAgg | units);
-        }
+        const uint32_t units = skip ? 0u : chunk_units(S);  // published by the chunk's last layer
         if (pend_j >= 0) place_copy(jobs[pend_j].out, jobs[pend_j].g, pend_units, slot, S);
         pend_j = -1;
         if (!skip) {

@@ -41,12 +41,12 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         if (scr->pre_status) return;  // set before this launch: uniform across the grid
         inv = quant_of(out);
     }
-    uint64_t* state = reinterpret_cast<uint64_t*>(scratch + kScratchStateOff);
     uint8_t* slot = scratch + g.scr_stage + kStageSlotBytes * (int64_t)blockIdx.x;
 
     if (threadIdx.x == 0) {
         S.ticket = atomicAdd(&scr->ticket, 1u);
         S.err = 0;
+        S.arrived = 0;
     }
     __syncthreads();
     int64_t c = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
@@ -77,10 +77,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
 #pragma unroll
             for (int i = 0; i < 32; i++) { h[i] = 0.0f; v[i] = 0.0f; }
         }
-        // this chunk's size goes out first, so that no look-back waits on it
-        // while this workgroup places its previous chunk
-        const uint32_t units = chunk_units(S);
-        if (threadIdx.x == 0) publish_state(state + c, kFlagAgg | units);
+        const uint32_t units = chunk_units(S);  // published by the chunk's last layer
         if (pend >= 0) place_copy(out, g, pend_units, slot, S);
         stage_chunk<RANK, VEC4, QM>(x, out, scratch, g, c, wave, lane, inv, F, myflag, nout, S, slot);
         pend = c;

@@ -527,11 +527,36 @@ __device__ __forceinline__ uint32_t classify_errors(const float* __restrict__ x,
 struct CompressLds {
     uint32_t err;
     uint32_t nnz[kLayers], nout[kLayers];
+    uint32_t arrived;  // waves whose layer of the current chunk is done
     uint64_t ticket;
     uint64_t excl;  // offset of the chunk being placed (16-B units), from the look-back
     // per wave: the bricks of its layer (as plane-step words)
     uint32_t w[kLayers][kPlanes * 4 * 64];
 };
+
+// Payload size of the chunk in S (16-B units): its nonzero bricks, then its
+// escape pairs padded to 16 bytes (none when the chunk holds more than
+// kChunkOutlierCap escapes: the stream then carries the OUTLIER_CAP status).
+__device__ __forceinline__ uint32_t chunk_units(const CompressLds& S)
+{
+    const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
+    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];  // each at most 8192: no overflow
+    const uint32_t kept = to > (uint32_t)kChunkOutlierCap ? 0u : to;
+    return tn + (kept + 1) / 2;
+}
+
+// Chunk state words are read and written with agent-scope atomics: the
+// workgroups that publish and read them run on different XCDs, whose L2
+// caches are not coherent with one another.
+__device__ __forceinline__ void publish_state(uint64_t* p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t peek_state(const uint64_t* p)
+{
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 
 // Tail of a wave's layer: the data-dependent status bits (NaN/Inf or an
 // overflowing product, seen in facc), the flags of the
@@ -564,6 +589,14 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, const ui
         S.nnz[wave] = nnz;
         S.nout[wave] = (uint32_t)nout;
         if (err) atomicOr(&S.err, err);
+        // the chunk's last wave to get here publishes its size at once: a
+        // size published after the workgroup barrier would wait for this
+        // workgroup's look-back, and other look-backs for it in turn
+        if (__hip_atomic_fetch_add(&S.arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == kLayers - 1) {
+            S.arrived = 0;  // the next chunk's waves arrive after a barrier
+            publish_state(reinterpret_cast<uint64_t*>(const_cast<uint8_t*>(scr) + kScratchStateOff) + c,
+                          kFlagAgg | chunk_units(S));
+        }
     }
     return nout;
 }
@@ -637,29 +670,6 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, const ui
     return layer_flags(x, scr, g, c, wave, lane, inv, nz, facc, log, S, F, myflag);
 }
 
-// Payload size of the chunk in S (16-B units): its nonzero bricks, then its
-// escape pairs padded to 16 bytes (none when the chunk holds more than
-// kChunkOutlierCap escapes: the stream then carries the OUTLIER_CAP status).
-__device__ __forceinline__ uint32_t chunk_units(const CompressLds& S)
-{
-    const uint32_t tn = S.nnz[0] + S.nnz[1] + S.nnz[2] + S.nnz[3];
-    const uint32_t to = S.nout[0] + S.nout[1] + S.nout[2] + S.nout[3];  // each at most 8192: no overflow
-    const uint32_t kept = to > (uint32_t)kChunkOutlierCap ? 0u : to;
-    return tn + (kept + 1) / 2;
-}
-
-// Chunk state words are read and written with agent-scope atomics: the
-// workgroups that publish and read them run on different XCDs, whose L2
-// caches are not coherent with one another.
-__device__ __forceinline__ void publish_state(uint64_t* p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t peek_state(const uint64_t* p)
-{
-    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // polls of a look-back before it gives up (each poll sleeps about 64 cycles
 // and waits for a load that bypasses the L2; far beyond any real wait)
 constexpr int kLookbackSpins = 1 << 18;
@@ -714,7 +724,8 @@ __device__ __forceinline__ bool lookback(const uint64_t* state, int64_t c, int l
 // past that the stream carries the OUTLIER_CAP status and no pairs are
 // written.  A layer with escapes is computed again out of line (its first
 // pass kept only the count) and writes its pairs behind those of the layers
-// before it.  The chunk's size was published right after the barrier.
+// before it.  The chunk's size was published by its last layer, before the
+// barrier.
 template <int RANK, bool VEC4, int QM = kQuantGrid>
 __device__ __forceinline__ void stage_chunk(const float* __restrict__ x, uint8_t* __restrict__ out,
                                             const uint8_t* __restrict__ scr, const Geom& g,
