@@ -702,8 +702,8 @@ def round_trips(xt, shape, eb, mode, buf, y, stream, reps, evict):
     microseconds, so these runs are not used for the end-to-end figures).
     Means in ms of: the whole compression and decompression calls, the range
     pass (k_minmax, REL; it also writes the header image and clears the
-    scratch), the main kernel (k_compress), the final
-    status pass (k_finish); the decompression call is its one kernel
+    scratch) and the main kernel (k_compress, whose last workgroup also
+    settles the status word); the decompression call is its one kernel
     (k_decompress: no error word is passed)."""
     import numpy as np
     import torch
@@ -731,8 +731,7 @@ def round_trips(xt, shape, eb, mode, buf, y, stream, reps, evict):
     torch.cuda.synchronize()
     t = lambda rs, a, b: float(np.mean([r[a].elapsed_time(r[b]) for r in rs]))
     return {"compress": t(rows, "c0", "c1"), "decompress": t(rows, "d0", "d1"),
-            "range": t(parts, "range_begin", "main_begin"), "main": t(parts, "main_begin", "main_end"),
-            "place": t(parts, "main_end", "done")}
+            "range": t(parts, "range_begin", "main_begin"), "main": t(parts, "main_begin", "main_end")}
 
 
 def config_rows(stream, reps, evict):
@@ -849,7 +848,6 @@ def main():
          "4N read + S_c written (placed payload)"),
         ("k_decompress", in_bytes + s_bytes, (rel["decompress"] + ab["decompress"]) / 2, "S_c read + 4N written"),
         ("k_minmax", in_bytes, rel["range"], "4N read (REL range pass)"),
-        ("k_finish", 0, (rel["place"] + ab["place"]) / 2, "none (the final status word)"),
     ]
     krows = []
     for name, alg, t_ms, what in kernels:

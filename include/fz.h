@@ -151,9 +151,10 @@ int fz_compress(const float *d_in, const fz_dims *dims, double eb, int eb_mode, 
  * optional hipEvent_t (as void*, NULL to skip) that fz_compress_timed
  * records on `stream`: range_begin before the value-range pass (REL mode;
  * after the header is initialised), main_begin right before the main
- * compression kernel, main_end right after it, done after the last kernel
- * (the device-wide prefix sum and the placement of the chunks).  Events
- * bracket launches, so an interval includes the launch gaps inside it. */
+ * compression kernel (which also places the chunks and settles the status
+ * word), main_end right after it, done after the last kernel (the same point
+ * for the per-field pipeline).  Events bracket launches, so an interval
+ * includes the launch gaps inside it. */
 typedef struct {
     void *range_begin, *main_begin, *main_end, *done;
 } fz_timing;

@@ -8,9 +8,9 @@
 // staged in its workgroup's slot and placed one chunk later, when the sizes
 // of the chunks before it are almost always published, so the look-back
 // rarely waits; then the slot, still in the cache, is copied to the chunk's
-// offset.  k_finish settles the status word.  REL mode runs k_minmax first
-// (the value range, plus k_init's work), and k_compress folds the range into
-// the eb parameters itself.
+// offset.  The grid's last workgroup to finish settles the status word.  REL
+// mode runs k_minmax first (the value range, plus k_init's work), and
+// k_compress folds the range into the eb parameters itself.
 #include <hip/hip_runtime.h>
 
 #include "fz.h"
@@ -50,7 +50,10 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     }
     __syncthreads();
     int64_t c = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)S.ticket);
-    if (c >= g.n_chunks) return;
+    if (c >= g.n_chunks) {  // the others took every chunk
+        finish_if_last(out, scratch);
+        return;
+    }
     float h[32], v[32];
     Lane l = lane_geo<RANK>(g, c, lane);
     prefetch<RANK, VEC4>(x, g, l, wave, h, v, swept_down<RANK>(wave));
@@ -89,12 +92,7 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
     if (wave == 0) place_lookback(out, scratch, g, pend, pend_units, S, lane);
     __syncthreads();  // the staged payload and its offset are complete
     place_copy(out, g, pend_units, slot, S);
-}
-
-// after every chunk of the field is placed: the final status word
-__global__ __launch_bounds__(64) void k_finish(uint8_t* __restrict__ out, const uint8_t* __restrict__ scratch)
-{
-    if (threadIdx.x == 0) finish_field(out, scratch);
+    finish_if_last(out, scratch);
 }
 
 __global__ __launch_bounds__(256) void k_init(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch, Geom g,
@@ -158,8 +156,6 @@ static hipError_t launch_rank(const float* x, uint8_t* out, uint8_t* scr, const 
                        nparts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t && (e = mark(t->main_end, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, out, scr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     return t ? mark(t->done, st) : hipSuccess;
 }
 
@@ -221,7 +217,7 @@ hipError_t launch_compress(const float* x, uint8_t* out, uint8_t* scr, const Geo
                            double eb, hipStream_t st, const Timing* t)
 {
     // REL: the range pass also initializes (the header image, the scratch), and
-    // the compression kernel folds the range itself: 3 launches with k_finish
+    // the compression kernel folds the range itself: 2 launches
     hipError_t e;
     double rel_eb = 0.0;
     int nparts = 0;

@@ -997,4 +997,30 @@ __device__ __forceinline__ void finish_field(uint8_t* __restrict__ out, const ui
     if (v & (kErrNonfinite | kErrEbRange)) *st = v & ~kErrOutlierCap;
 }
 
+// The same inside the per-field compression kernel, by thread 0 of each
+// workgroup as it ends (after its last placement and barrier): the last
+// workgroup of the grid to count itself done settles the status word, so
+// that no launch of its own is needed.  The status word and the count are
+// only touched with agent-scope atomics, which every XCD sees in one order
+// (their L2 caches are not coherent with one another, so nothing here may
+// rely on them).  Thread 0 set its workgroup's status bits; an explicit wait
+// for its outstanding memory operations (not an agent-scope release, which
+// adds an L2 write-back at every workgroup's end: +9 us on 512^3) makes those
+// atomics complete before the count is issued, and the last workgroup
+// reads and clears the word only after its count has returned.  Workgroups
+// that return because the range pass failed (pre_status) do not count;
+// nothing is settled then.
+__device__ __forceinline__ void finish_if_last(uint8_t* __restrict__ out, uint8_t* __restrict__ scratch)
+{
+    if (threadIdx.x != 0) return;
+    Scratch* scr = reinterpret_cast<Scratch*>(scratch);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // no memory operation moves below this point
+    __builtin_amdgcn_s_waitcnt(0);  // and every one of this thread's has completed (the fence alone emits no wait)
+    if (__hip_atomic_fetch_add(&scr->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gridDim.x - 1) return;
+    uint32_t* st = reinterpret_cast<uint32_t*>(out + kOffStatus);
+    const uint32_t v = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v & (kErrNonfinite | kErrEbRange))
+        __hip_atomic_fetch_and(st, ~kErrOutlierCap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace fz

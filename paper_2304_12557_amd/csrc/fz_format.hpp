@@ -60,7 +60,8 @@ constexpr uint32_t kErrInternal = 0x80000000u;  // a consistency check of the li
 struct Scratch {
     uint32_t ticket;      // chunk tickets, in launch order
     uint32_t pre_status;  // errors found before the main pass (REL params)
-    uint32_t pad[14];
+    uint32_t done;        // compression workgroups that have finished
+    uint32_t pad[13];
     // followed by a copy of the Geom at byte 64 (read by out-of-line device
     // code) and by uint64_t state[n_chunks] at byte kScratchStateOff
 };
