@@ -6,6 +6,8 @@ fp32 operation order on both sides).  Sizes span several chunks and ragged
 tails; edge cases cover single elements, constant and zero fields, escapes,
 and the data-dependent error bits.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -158,6 +160,26 @@ def test_status_precedence():
         _, st = O.compress(bad, eb, O.EB_ABS)
         buf, _ = gpu_compress(bad, eb, O.EB_ABS)
         assert fz.stream_info(buf)["status"] == st == want
+
+
+@pytest.mark.parametrize("where", [(0, 0, 0), (63, 511, 1023), (40, 300, 700)])
+def test_status_precedence_full_grid(where):
+    """The same on 1024 chunks, more than the persistent grid has
+    workgroups: every chunk holds more escapes than the cap allows, and one
+    chunk also a NaN.  The grid's last workgroup to finish settles the status
+    word, whichever workgroups set its bits, so the escape-cap bit is never
+    reported with NONFINITE."""
+    rng = np.random.default_rng(6)
+    w = (rng.standard_normal((64, 512, 1024)) * 1e6).astype(np.float32)
+    w[where] = np.nan
+    print("full-grid precedence", where, flush=True)
+    _, st = O.compress(w, 0.5, O.EB_ABS, threads=min(os.cpu_count() or 1, 16))
+    buf, _ = gpu_compress(w, 0.5, O.EB_ABS)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_NONFINITE
+    w[where] = 0.0
+    _, st = O.compress(w, 0.5, O.EB_ABS, threads=min(os.cpu_count() or 1, 16))
+    buf, _ = gpu_compress(w, 0.5, O.EB_ABS)
+    assert fz.stream_info(buf)["status"] == st == O.ERR_OUTLIER_CAP
 
 
 @pytest.mark.parametrize("where", ["first", "last", "tail", "middle"])
