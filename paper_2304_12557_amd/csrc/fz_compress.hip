@@ -66,7 +66,13 @@ __global__ __launch_bounds__(256, 2) void k_compress(const float* __restrict__ x
         uint32_t tk;  // thread 0 only: a value on the other lanes would need a copy that waits for the atomic
         if (threadIdx.x == 0) tk = atomicAdd(&scr->ticket, 1u);
         uint64_t F[16], myflag;
+        // wave priority: the layer at the lowest, the serial part after it
+        // (look-back, barrier, placement, staging) at a higher one, so that
+        // its few instructions issue first when the CU's other workgroup is in
+        // its layer (measured: 512^3 compression about 2 us faster)
+        __builtin_amdgcn_s_setprio(0);
         const int nout = chunk_layer<RANK, VEC4, QM>(x, scratch, g, c, l, wave, lane, inv, h, v, S, F, myflag);
+        __builtin_amdgcn_s_setprio(3);
         // the previous chunk's offset: wave 0 looks back while the other waves finish their layers
         if (pend >= 0 && wave == 0) place_lookback(out, scratch, g, pend, pend_units, S, lane);
         if (threadIdx.x == 0) S.ticket = tk;
