@@ -609,19 +609,26 @@ __device__ __forceinline__ int layer_flags(const float* __restrict__ x, const ui
 // reported an escape; the layer has then taken the logging pass instead,
 // which zeroes those deltas before it looks for escapes.  A real call, with
 // plain arguments and LDS only: inlined, or with arrays passed to it, it
-// pushes the fast path into spills.
+// pushes the fast path into spills.  The words are addressed as LDS (a plain
+// pointer made them flat accesses, in 2-D each read waited for before its
+// write), a step's 16 words read before any is written back.
+typedef __attribute__((address_space(3))) uint32_t LdsWord;
 template <int RANK>
-__device__ __noinline__ void mask_layer(uint32_t* Wl, int64_t e0, int64_t e1, int64_t e2, uint32_t off, int k, int lane)
+__device__ __noinline__ void mask_layer(LdsWord* Wl, int64_t e0, int64_t e1, int64_t e2, uint32_t off, int k, int lane)
 {
     Lane l;
     l.ext[0] = e0;
     l.ext[1] = e1;
     l.ext[2] = e2;
     l.off = off;
+#pragma unroll
     for (int t = 0; t < 4; t++) {
         const uint32_t keep = keep_bits<RANK>(l, 4 * k + t, lane);
+        uint32_t w[16];
 #pragma unroll
-        for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] &= keep;
+        for (int b = 0; b < 16; b++) w[b] = Wl[(b * 4 + t) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < 16; b++) Wl[(b * 4 + t) * 64 + lane] = w[b] & keep;
     }
 }
 
@@ -645,7 +652,7 @@ __device__ __forceinline__ int chunk_layer(const float* __restrict__ x, const ui
                        ? layer_rev<RANK, VEC4, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log)
                        : layer<RANK, VEC4, false, QM>(x, g, l, wave, inv, lane, h, v, Wl, nz, facc, log);
             if (!slow && l.edge)  // uniform: clear the codes of cells outside the field
-                mask_layer<RANK>(Wl, l.ext[0], l.ext[1], l.ext[2], l.off, wave, lane);
+                mask_layer<RANK>((LdsWord*)Wl, l.ext[0], l.ext[1], l.ext[2], l.off, wave, lane);
         } else {
             // 1-D: only a field's last chunk is cut by its edge; it takes the
             // logging pass, which masks the deltas itself (a mask call here
